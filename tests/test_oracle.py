@@ -1,0 +1,361 @@
+"""Pins for the FP64 CPU oracle (no GPU needed).
+
+Each test ties the oracle to something other than itself: closed forms of the
+DFT, an independent FFT library, brute force in plain Python, exact invariants
+of the discrete convolution, statements made in the paper, and the analytic
+potentials of Sec. 4.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1106_0557_amd import sources
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_problems.json")
+RNG = np.random.default_rng(20110602)
+
+
+# ------------------------------------------------------------------ 1D DFT --
+
+def test_dft_closed_forms(oracle_lib):
+    o = oracle_lib
+    for L in (1, 2, 3, 5, 8, 12, 30):
+        # impulse at j0 -> exp(-2 pi i j0 k / L)
+        for j0 in range(L):
+            x = np.zeros(L, complex)
+            x[j0] = 1.0
+            k = np.arange(L)
+            want = np.exp(-2j * np.pi * j0 * k / L)
+            np.testing.assert_allclose(o.dft_1d(x), want, atol=1e-14)
+        # constant -> L at k = 0
+        want = np.zeros(L, complex)
+        want[0] = L
+        np.testing.assert_allclose(o.dft_1d(np.ones(L, complex)), want, atol=1e-13)
+        # cosine of frequency m -> L/2 at k = m and k = L - m
+        for m in range(1, (L + 1) // 2):
+            j = np.arange(L)
+            want = np.zeros(L, complex)
+            want[m] += L / 2
+            want[L - m] += L / 2
+            np.testing.assert_allclose(o.dft_1d(np.cos(2 * np.pi * m * j / L)), want, atol=1e-12)
+
+
+@pytest.mark.parametrize("L", list(range(1, 41)) + [48, 64, 72, 96, 100, 128, 77, 121])
+def test_fft_matches_textbook_dft(oracle_lib, L):
+    x = RNG.normal(size=L) + 1j * RNG.normal(size=L)
+    for sign in (-1, 1):
+        a = oracle_lib.fft_1d(x, sign)
+        b = oracle_lib.dft_1d(x, sign)
+        assert np.abs(a - b).max() <= 1e-13 * max(1.0, np.abs(b).max())
+
+
+@pytest.mark.parametrize("L", [64, 96, 128, 192, 256, 384, 512, 1024, 1152, 999])
+def test_fft_matches_numpy(oracle_lib, L):
+    x = RNG.normal(size=L) + 1j * RNG.normal(size=L)
+    a = oracle_lib.fft_1d(x)
+    b = np.fft.fft(x)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    # inverse convention: unnormalised exp(+...), so F^+ F = L
+    back = oracle_lib.fft_1d(a, +1) / L
+    assert np.abs(back - x).max() <= 1e-13 * np.abs(x).max()
+    # Parseval
+    assert abs(np.sum(np.abs(a) ** 2) / L - np.sum(np.abs(x) ** 2)) <= 1e-12 * np.sum(np.abs(x) ** 2)
+
+
+def test_fft3d_matches_numpy(oracle_lib):
+    a = RNG.normal(size=(6, 10, 12)) + 1j * RNG.normal(size=(6, 10, 12))
+    got = oracle_lib.fft_3d(a, -1)
+    want = np.fft.fftn(a)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    got = oracle_lib.fft_3d(a, +1)
+    want = np.fft.ifftn(a) * a.size
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+# -------------------------------------------------------- Green's function --
+
+@pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (0.3, 0.2, 0.5), (0.1, 0.4, 0.05), (2.0, 2.0, 3.0)])
+def test_self_cell_is_largest_off_origin_value(oracle_lib, h):
+    """Sec. 2.1: G(0,0,0) is set equal to the largest off-origin value on the mesh."""
+    g0 = oracle_lib.green_value(0, 0, 0, h)
+    axis = int(np.argmin(h))
+    step = [0, 0, 0]
+    step[axis] = 1
+    assert g0 == pytest.approx(oracle_lib.green_value(*step, h), rel=1e-15)
+    others = [abs(oracle_lib.green_value(p, q, r, h))
+              for p in range(4) for q in range(4) for r in range(4) if p + q + r]
+    assert abs(g0) >= max(others) * (1 - 1e-15)
+    assert g0 < 0
+
+
+def test_self_cell_unit_spacing_is_hockney(oracle_lib):
+    """Sec. 2.1: for unit spacings the value reduces (up to sign and 4 pi) to Hockney's G(0)=1."""
+    assert -4 * math.pi * oracle_lib.green_value(0, 0, 0, (1, 1, 1)) == pytest.approx(1.0, rel=1e-15)
+
+
+def test_green_dimensional_scaling(oracle_lib):
+    """G carries the cell volume over a distance, so scaling every h by s scales G by s^2."""
+    h = np.array([0.3, 0.2, 0.5])
+    for p, q, r in [(0, 0, 0), (1, 2, 3), (5, 0, 1)]:
+        assert oracle_lib.green_value(p, q, r, 3.0 * h) == pytest.approx(
+            9.0 * oracle_lib.green_value(p, q, r, h), rel=1e-14)
+
+
+@pytest.mark.parametrize("n", [(4, 4, 4), (5, 3, 6), (2, 7, 3)])
+def test_doubled_green_is_periodic_replication(oracle_lib, n):
+    """Sec. 2.1: periodic replication of the doubled mesh gives Eq. (greens2) on -n..n."""
+    h = (0.3, 0.2, 0.5)
+    nx, ny, nz = n
+    g = oracle_lib.green_doubled(n, h)
+    for r in range(-nz, nz + 1):
+        for q in range(-ny, ny + 1):
+            for p in range(-nx, nx + 1):
+                want = oracle_lib.green_value(abs(p), abs(q), abs(r), h)
+                assert g[r % (2 * nz), q % (2 * ny), p % (2 * nx)] == want
+
+
+def test_green_hat_real_even_and_dc(oracle_lib):
+    n = (6, 5, 4)
+    h = (0.3, 0.2, 0.5)
+    nx, ny, nz = n
+    ghat, imag_max, abs_max = oracle_lib.green_hat_octant(n, h)
+    assert imag_max <= 1e-13 * abs_max
+    g = oracle_lib.green_doubled(n, h)
+    full = np.fft.fftn(g) / g.size
+    # evenness in each axis
+    assert np.abs(full - full[::-1, :, :].take(np.arange(-1, 2 * nz - 1), axis=0)).max() <= 1e-13 * abs_max
+    # octant agrees with an independent library transform
+    assert np.abs(ghat - full.real[: nz + 1, : ny + 1, : nx + 1]).max() <= 1e-13 * abs_max
+    # DC term is the mean of the doubled G (definition of the DFT at k = 0)
+    assert ghat[0, 0, 0] == pytest.approx(g.sum() / g.size, rel=1e-13)
+
+
+# --------------------------------------------------------------- the solve --
+
+def _brute_force_direct(S, h):
+    """Plain-Python O(N^2) sum of Eq. (convolution) with Eq. (greens2) -- an independent check."""
+    nz, ny, nx = S.shape
+    hx, hy, hz = h
+    vol = hx * hy * hz
+    out = np.zeros_like(S)
+    for tz in range(nz):
+        for ty in range(ny):
+            for tx in range(nx):
+                acc = 0.0
+                for z in range(nz):
+                    for y in range(ny):
+                        for x in range(nx):
+                            dx, dy, dz = tx - x, ty - y, tz - z
+                            if dx == dy == dz == 0:
+                                g = -vol / (4 * math.pi * min(hx, hy, hz))
+                            else:
+                                g = -vol / (4 * math.pi * math.sqrt((hx * dx) ** 2 + (hy * dy) ** 2 + (hz * dz) ** 2))
+                            acc += g * S[z, y, x]
+                out[tz, ty, tx] = acc
+    return out
+
+
+def test_direct_sum_matches_brute_force(oracle_lib):
+    h = (0.3, 0.2, 0.5)
+    S = RNG.uniform(-1, 1, size=(3, 2, 4))
+    want = _brute_force_direct(S, h)
+    got = oracle_lib.direct(S, h)
+    assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max()
+    # sampled targets give the same numbers
+    idx = np.array([0, 5, 23, 7])
+    assert np.array_equal(oracle_lib.direct(S, h, idx), got.ravel()[idx])
+
+
+@pytest.mark.parametrize("n,h", [((4, 4, 4), (1, 1, 1)), ((6, 5, 7), (0.3, 0.2, 0.5)),
+                                 ((12, 8, 10), (0.05, 0.07, 0.06)), ((16, 16, 16), 1 / 16)])
+def test_fft_solve_matches_direct_sum(oracle_lib, n, h):
+    """The mesh-doubled periodic convolution equals the aperiodic sum exactly (Sec. 2.1)."""
+    from oracle import norms
+
+    S = RNG.uniform(-1, 1, size=n[::-1])
+    a = oracle_lib.solve_fft(S, h)
+    b = oracle_lib.direct(S, h)
+    assert norms.rel_l2(a, b) <= 1e-13
+    assert norms.rel_max(a, b) <= 1e-13
+
+
+@pytest.mark.slow
+def test_config1_fft_matches_full_direct_sum(oracle_lib):
+    from oracle import norms
+
+    n, h, S = sources.config1()
+    S = S.numpy()
+    a = oracle_lib.solve_fft(S, h)
+    b = oracle_lib.direct(S, h)
+    assert norms.rel_l2(a, b) <= 1e-13
+    assert norms.rel_max(a, b) <= 1e-13
+
+
+@pytest.mark.parametrize("c", [(0, 0, 0), (3, 1, 2), (4, 5, 6)])
+def test_impulse_response_reproduces_green(oracle_lib, c):
+    """S = delta at cell c gives Phi(i) = G(i - c): pins padding, reflection and normalisation."""
+    nx, ny, nz = 5, 6, 7
+    h = (0.3, 0.2, 0.5)
+    S = np.zeros((nz, ny, nx))
+    S[c[2], c[1], c[0]] = 1.0
+    phi = oracle_lib.solve_fft(S, h)
+    want = np.empty_like(phi)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                want[z, y, x] = oracle_lib.green_value(abs(x - c[0]), abs(y - c[1]), abs(z - c[2]), h)
+    assert np.abs(phi - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_operator_invariants(oracle_lib):
+    n = (7, 6, 5)
+    h = (0.3, 0.2, 0.5)
+    S1 = RNG.uniform(-1, 1, size=n[::-1])
+    S2 = RNG.uniform(-1, 1, size=n[::-1])
+    P1 = oracle_lib.solve_fft(S1, h)
+    P2 = oracle_lib.solve_fft(S2, h)
+    scale = np.abs(P1).max()
+    # linearity
+    P12 = oracle_lib.solve_fft(2.0 * S1 - 3.0 * S2, h)
+    assert np.abs(P12 - (2 * P1 - 3 * P2)).max() <= 1e-13 * scale
+    # reciprocity: G is symmetric
+    assert abs(np.vdot(S1, P2) - np.vdot(S2, P1)) <= 1e-12 * abs(np.vdot(S1, P2))
+    # mirror symmetry: G is even in each axis
+    for ax in range(3):
+        Pm = oracle_lib.solve_fft(np.flip(S1, axis=ax), h)
+        assert np.abs(Pm - np.flip(P1, axis=ax)).max() <= 1e-13 * scale
+    # translation: a source that stays inside the box shifts its potential exactly
+    S = np.zeros(n[::-1])
+    S[1:3, 1:4, 2:5] = RNG.uniform(-1, 1, size=(2, 3, 3))
+    P = oracle_lib.solve_fft(S, h)
+    Ps = oracle_lib.solve_fft(np.roll(S, shift=(1, 2, 1), axis=(0, 1, 2)), h)
+    assert np.abs(Ps[1:, 2:, 1:] - P[:-1, :-2, :-1]).max() <= 1e-13 * np.abs(P).max()
+
+
+def test_axis_permutation_symmetry(oracle_lib):
+    """With isotropic spacing, transposing the source transposes the potential."""
+    S = RNG.uniform(-1, 1, size=(5, 6, 7))
+    P = oracle_lib.solve_fft(S, 0.1)
+    Pt = oracle_lib.solve_fft(np.ascontiguousarray(S.transpose(2, 0, 1)), 0.1)
+    assert np.abs(Pt - P.transpose(2, 0, 1)).max() <= 1e-13 * np.abs(P).max()
+    # anisotropic spacing must follow the axis: permuting h along with S keeps Phi consistent
+    h = (0.3, 0.2, 0.5)
+    Pa = oracle_lib.solve_fft(S, h)
+    Pb = oracle_lib.solve_fft(np.ascontiguousarray(S.transpose(2, 0, 1)), (h[1], h[2], h[0]))
+    assert np.abs(Pb - Pa.transpose(2, 0, 1)).max() <= 1e-13 * np.abs(Pa).max()
+
+
+# ----------------------------------------------------------- closed forms --
+
+def _lap(f, x, y, z, d=1e-3):
+    return (f(x + d, y, z) + f(x - d, y, z) + f(x, y + d, z) + f(x, y - d, z) + f(x, y, z + d)
+            + f(x, y, z - d) - 6 * f(x, y, z)) / (d * d)
+
+
+def test_sphere_closed_form_is_a_potential():
+    from oracle import closed_forms as cf
+
+    R, Grho = 0.7, 1.3
+    f = lambda x, y, z: cf.phi_sphere(x, y, z, R, Grho)  # noqa: E731
+    # Poisson: Laplacian = 4 pi G rho inside, 0 outside
+    assert _lap(f, 0.1, 0.2, -0.3) == pytest.approx(4 * math.pi * Grho, rel=1e-5)
+    assert abs(_lap(f, 0.9, 0.5, -0.4)) <= 1e-4
+    # continuity at the surface and the far field -G M / r
+    d = np.array([0.3, -0.5, 0.6])
+    d /= np.linalg.norm(d)
+    assert f(*(R * (1 - 1e-12) * d)) == pytest.approx(f(*(R * (1 + 1e-12) * d)), rel=1e-9)
+    M = 4 / 3 * math.pi * R**3
+    assert f(*(1e4 * d)) == pytest.approx(-Grho * M / 1e4, rel=1e-12)
+
+
+def test_spheroid_closed_form_is_a_potential():
+    from oracle import closed_forms as cf
+
+    a, b, Grho = 0.5, 0.5 * math.sqrt(1 - 0.81), 1.0
+    f = lambda x, y, z: cf.phi_spheroid(x, y, z, a, b, Grho)  # noqa: E731
+    assert _lap(f, 0.1, 0.05, 0.03) == pytest.approx(4 * math.pi * Grho, rel=1e-5)
+    assert abs(_lap(f, 0.6, 0.1, 0.2)) <= 1e-4
+    assert abs(_lap(f, 0.05, 0.1, 0.4)) <= 1e-4
+    # continuity across the surface in several directions
+    for th in (0.1, 0.7, 1.3, 1.5):
+        p = np.array([a * math.sin(th), 0.0, b * math.cos(th)])
+        assert f(*(p * (1 - 1e-10))) == pytest.approx(f(*(p * (1 + 1e-10))), rel=1e-8)
+    # far field -G M / r with M = 4/3 pi a^2 b rho
+    M = 4 / 3 * math.pi * a * a * b
+    assert f(3e3, 1e3, 2e3) == pytest.approx(-Grho * M / math.sqrt(14e6), rel=1e-6)
+    # nearly spherical spheroid approaches the sphere
+    g = cf.phi_spheroid(0.2, 0.3, 0.4, 0.5, 0.5 * (1 - 1e-7), Grho)
+    assert g == pytest.approx(cf.phi_sphere(0.2, 0.3, 0.4, 0.5, Grho), rel=1e-5)
+    g = cf.phi_spheroid(0.6, 0.3, 0.4, 0.5, 0.5 * (1 - 1e-7), Grho)
+    assert g == pytest.approx(cf.phi_sphere(0.6, 0.3, 0.4, 0.5, Grho), rel=1e-5)
+
+
+# ----------------------------------------------------- physics convergence --
+
+def _paper_problem(kind, n, sub=4):
+    P = json.load(open(GOLDEN))
+    from oracle import closed_forms as cf
+
+    if kind == "sphere":
+        p = P["sphere"]
+        lo, hi = p["box_lo"], p["box_hi"]
+        h = (hi - lo) / n
+        S = sources.sphere(n, h, p["radius"], 0.0, 4 * math.pi * p["rho"], sub=sub, origin=(lo,) * 3).numpy()
+        x = lo + (np.arange(n) + 0.5) * h
+        ref = cf.phi_sphere(x[None, None, :], x[None, :, None], x[:, None, None], p["radius"], p["rho"])
+    else:
+        p = P["spheroid"]
+        lo, hi = p["box_lo"], p["box_hi"]
+        h = (hi - lo) / n
+        a = p["a"]
+        b = a * math.sqrt(1 - p["e"] ** 2)
+        S = sources.spheroid(n, h, a, b, 0.0, 4 * math.pi * p["rho"], sub=sub, origin=(lo,) * 3).numpy()
+        x = lo + (np.arange(n) + 0.5) * h
+        ref = cf.phi_spheroid(x[None, None, :], x[None, :, None], x[:, None, None], a, b, p["rho"])
+    return S, h, ref
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind", ["sphere", "spheroid"])
+def test_paper_problems_converge_better_than_first_order(oracle_lib, kind):
+    """Sec. 4.1/4.2: the L1 error against the analytic potential falls faster than first order."""
+    from oracle import norms
+
+    errs = []
+    for n in (24, 48, 96):
+        S, h, ref = _paper_problem(kind, n)
+        errs.append(norms.l1(oracle_lib.solve_fft(S, h), ref))
+    order = math.log2(errs[0] / errs[-1]) / 2
+    assert errs[0] > errs[1] > errs[2]
+    assert order > 1.0
+    assert errs[-1] < 1e-3
+
+
+def test_config1_sphere_close_to_closed_form(oracle_lib):
+    from oracle import closed_forms as cf, norms
+
+    n, h, S = sources.config1()
+    phi = oracle_lib.solve_fft(S.numpy(), h)
+    x = (np.arange(n) + 0.5) * h - 0.5
+    ref = cf.phi_sphere(x[None, None, :], x[None, :, None], x[:, None, None], 0.25, 1 / (4 * math.pi))
+    assert norms.l1(phi, ref) < 0.03
+    assert norms.rel_max(phi, ref) < 0.03
+
+
+def test_anisotropic_rectangular_grid_follows_the_axes(oracle_lib):
+    """A sphere on a (32, 24, 16) grid over the unit box: h differs per axis (Eq. greens2)."""
+    from oracle import closed_forms as cf, norms
+
+    n = (32, 24, 16)
+    h = tuple(1.0 / v for v in n)
+    S = sources.sphere(n, h, 0.3, 0.5, 4 * math.pi, sub=4).numpy()
+    phi = oracle_lib.solve_fft(S, h)
+    x, y, z = ((np.arange(v) + 0.5) / v - 0.5 for v in n)
+    ref = cf.phi_sphere(x[None, None, :], y[None, :, None], z[:, None, None], 0.3, 1.0)
+    assert norms.l1(phi, ref) < 0.01
+    # the wrong axis assignment of h is clearly detected
+    wrong = oracle_lib.solve_fft(S, h[::-1])
+    assert norms.l1(wrong, ref) > 10 * norms.l1(phi, ref)
