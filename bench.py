@@ -1,0 +1,285 @@
+#!/usr/bin/env python3
+"""Benchmark of the isolated Poisson solve (arXiv:1106.0557) on one MI355X.
+
+Headline workload: the 128^3 mesh padded to 256^3 (homogeneous oblate spheroid,
+a=0.3, b=0.15 of the box, S = 4 pi inside).  One timed step = one batch of
+``--batch`` independent FP32 solves issued through the grouped pass launches
+that the serving loop uses (five launches per step, each over every problem of
+the batch), with all inputs resident in HBM.  Beside it: the FP64 plain path
+(sequential single solves, per-solve HIP events), the continuous-batching
+serving loop on a Poisson arrival trace, and the FP64 CPU oracle timed on this
+host's cores.
+
+Prints one JSON line.  ``value`` = FP32 served solves/s over the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "solves/s + effective HBM GB/s at 256^3 (FP32 served vs FP64 plain); p50/p99"
+KERNEL_SOURCES = ("paper_1106_0557_amd/csrc/pspfft_kernels.hip", "paper_1106_0557_amd/csrc/pspfft_runtime.cpp",
+                  "paper_1106_0557_amd/csrc/internal.h")
+
+
+def algorithmic_bytes(n: int, real: int) -> int:
+    """Pad-aware five-pass model: read S and write Phi, 12 complex n^2 (n+1) of
+    workspace traffic, the (n+1)^3 spectrum read once."""
+    c = 2 * real
+    return 2 * real * n**3 + 12 * c * n * n * (n + 1) + real * (n + 1) ** 3
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    f = math.floor(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, n: int, batch: int):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary, or None when it is missing or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if data.get("source_hash") != source_hash():
+        return None
+    entry = data.get("kernels", {}).get(kernel)
+    if not entry or entry.get("n") != n or entry.get("batch") != batch:
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--batch", type=int, default=16, help="FP32 solves per served step")
+    ap.add_argument("--fp64-solves", type=int, default=2500, help="sequential FP64 plain solves (paper: 2500)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the CPU oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
+        return
+
+    import paper_1106_0557_amd as ps
+    from paper_1106_0557_amd import sources
+
+    n = args.n
+    B = args.batch
+    stream = torch.cuda.current_stream()
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+
+    # ---------------------------------------------------------------- inputs
+    log(f"[bench] n={n} batch={B}: building plans and sources")
+    _, h, S64 = sources.config2(n=n)
+    plan32 = ps.Plan(n, n, n, h=h, dtype=torch.float32)
+    plan64 = ps.Plan(n, n, n, h=h, dtype=torch.float64)
+    S32_dev = S64.to("cuda", torch.float32)
+    S64_dev = S64.to("cuda", torch.float64)
+    ws = [plan32.workspace() for _ in range(B)]
+    S_list = [S32_dev.clone() for _ in range(B)]
+    P_list = [torch.empty_like(S32_dev) for _ in range(B)]
+    torch.cuda.synchronize()
+
+    # --------------------------------------------- FP32 served batch (timed)
+    pass_names = ps.PASS_NAMES
+
+    def step(evs=None):
+        for p in range(5):
+            if evs is not None:
+                evs[p].record(stream)
+            ps.pass_batched(p, ws, S=S_list, Phi=P_list, stream=stream)
+        if evs is not None:
+            evs[5].record(stream)
+
+    log(f"[bench] warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev_sets = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(ev_sets[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_pass_ms = [[evs[p].elapsed_time(evs[p + 1]) for evs in ev_sets] for p in range(5)]
+    step_ms = [evs[0].elapsed_time(evs[5]) for evs in ev_sets]
+    solves32 = B * args.steps / wall
+    bytes32 = algorithmic_bytes(n, 4)
+    eff32 = bytes32 * solves32 / 1e9
+    avg_pass = [sum(v) / len(v) for v in per_pass_ms]
+    dom = max(range(5), key=lambda p: avg_pass[p])
+    dom_bytes = plan32.pass_bytes(dom) * B
+    dom_gbs = dom_bytes / (avg_pass[dom] * 1e-3) / 1e9
+    log(f"[bench] fp32 served: {solves32:.1f} solves/s, {eff32:.0f} GB/s effective; passes (ms) "
+        + ", ".join(f"{pass_names[p]}={avg_pass[p]:.4f}" for p in range(5)))
+
+    # accuracy of the FP32 served result (last step) against the GPU FP64 solve
+    phi64 = plan64.solve(S64_dev)
+    torch.cuda.synchronize()
+    d = (P_list[0].double() - phi64)
+    acc32 = {"rel_l2_vs_gpu_fp64": float(d.norm() / phi64.norm()),
+             "rel_max_vs_gpu_fp64": float(d.abs().max() / phi64.abs().max())}
+
+    # ---------------------------------------------------- FP64 plain (timed)
+    out64 = torch.empty_like(S64_dev)
+    for _ in range(20):
+        plan64.solve(S64_dev, out=out64)
+    torch.cuda.synchronize()
+    R = args.fp64_solves
+    evs64 = [torch.cuda.Event(enable_timing=True) for _ in range(R + 1)]
+    log(f"[bench] fp64 plain: {R} sequential solves")
+    t0 = time.perf_counter()
+    evs64[0].record(stream)
+    for i in range(R):
+        plan64.solve(S64_dev, out=out64)
+        evs64[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall64 = time.perf_counter() - t0
+    lat64 = [evs64[i].elapsed_time(evs64[i + 1]) for i in range(R)]
+    solves64 = R / wall64
+    eff64 = algorithmic_bytes(n, 8) * solves64 / 1e9
+
+    # ----------------------------------------------- serving loop (Poisson)
+    serve = None
+    if not args.no_serve:
+        try:
+            from paper_1106_0557_amd import serve as serve_mod
+
+            serve = serve_mod.bench_served(n=n, dtype=torch.float32, plan=plan32, source=S32_dev,
+                                           duration_s=3.0, log=log)
+        except ImportError:
+            serve = None
+
+    # -------------------------------------------------------- CPU oracle leg
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        from oracle import norms
+
+        log("[bench] cpu oracle sample")
+        S_np = S64.numpy()
+        times = []
+        ref = None
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            ref = oracle.solve_fft(S_np, h)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start + times[-1] > args.cpu_seconds or len(times) >= 20:
+                break
+        cpu = {"value": len(times) / sum(times), "unit": "solves/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"{len(times)} full FP64 oracle solves (naive mixed-radix FFT convolution on the "
+                         f"{2 * n}^3 padded mesh, OpenMP) of the same {n}^3 spheroid source",
+               "cpu_model": platform.processor() or platform.machine()}
+        acc32["rel_l2_vs_oracle"] = norms.rel_l2(P_list[0].double().cpu().numpy(), ref)
+        acc32["rel_max_vs_oracle"] = norms.rel_max(P_list[0].double().cpu().numpy(), ref)
+        o64 = out64.cpu().numpy()
+        acc64 = {"rel_l2_vs_oracle": norms.rel_l2(o64, ref), "rel_max_vs_oracle": norms.rel_max(o64, ref)}
+    else:
+        acc64 = None
+
+    traffic = load_traffic(f"pass_{pass_names[dom]}", n, B)
+    result = {
+        "metric": METRIC,
+        "value": round(solves32, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"isolated Poisson solve, {n}^3 mesh padded to {2 * n}^3 (homogeneous oblate "
+                               f"spheroid a=0.3 b=0.15, S=4pi inside), FP32 served path, {B} solves per step "
+                               f"in grouped launches",
+                   "n": n, "padded": 2 * n, "batch_per_step": B, "parallelism": "single-gpu"},
+        "effective_GBps": round(eff32, 1),
+        "roofline_frac_effective": round(eff32 / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes_per_solve": bytes32,
+        "step_ms_p50": round(percentile(step_ms, 50), 5),
+        "step_ms_p99": round(percentile(step_ms, 99), 5),
+        "pass_ms_avg": {pass_names[p]: round(avg_pass[p], 5) for p in range(5)},
+        "fp32_accuracy": acc32,
+        "fp64_plain": {"solves_per_s": round(solves64, 2), "effective_GBps": round(eff64, 1),
+                       "roofline_frac_effective": round(eff64 / HBM_PEAK_GBS, 4),
+                       "latency_ms_p50": round(percentile(lat64, 50), 5),
+                       "latency_ms_p99": round(percentile(lat64, 99), 5),
+                       "solves_timed": R, "accuracy": acc64},
+        "roofline": {"bound": "hbm", "kernel": f"pass_kernel ({pass_names[dom]})",
+                     "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes_per_launch": dom_bytes,
+                     "avg_launch_ms": round(avg_pass[dom], 5),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "served": serve,
+        "kernel_source_hash": source_hash(),
+    }
+    print(json.dumps(result), flush=True)
+    for w in ws:
+        w.close()
+    plan32.close()
+    plan64.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * pspfft.h -- C ABI of an MI355X (gfx950) implementation of the isolated
+ * Poisson solve of Budiardja & Cardall, "Parallel FFT-based Poisson Solver for
+ * Isolated Three-dimensional Systems" (arXiv:1106.0557, PSPFFT).
+ *
+ * The operation (Sec. 2.1).  Given a source S on an nx x ny x nz mesh with
+ * constant spacings (hx, hy, hz), the library returns the potential
+ *
+ *     Phi_i = sum_{i' in mesh} G(i - i') S_{i'},
+ *     G(p,q,r) = -hx hy hz / (4 pi sqrt(hx^2 p^2 + hy^2 q^2 + hz^2 r^2)),  (p,q,r) != 0,
+ *     G(0,0,0) = -hx hy hz / (4 pi min(hx, hy, hz)),
+ *
+ * i.e. Eq. (greens2) evaluated at integer index offsets with the self-cell value
+ * of Eq. (greens_function), which solves del^2 Phi = S with Phi -> 0 at infinity
+ * (Eq. (poisson)) to discretisation error.  It is evaluated with Hockney's mesh
+ * doubling (Sec. 2.1, Fig. 1): S is zero-padded to (2nx)(2ny)(2nz), transformed,
+ * multiplied by the transform of the doubled Green's function, transformed back,
+ * and the active octant is kept.  The transform of G is computed once, when the
+ * plan is created (Sec. 2.2.2: computed at initialisation and stored permanently).
+ *
+ * Layout.  S and Phi are dense arrays of nx*ny*nz reals in the plan's precision,
+ * x fastest: element (x, y, z) is at index (z*ny + y)*nx + x.  This is the
+ * paper's convention of the first array dimension being x (Sec. 3.2).  A torch
+ * tensor of shape (nz, ny, nx), contiguous, has this layout.
+ *
+ * Memory.  Every data pointer (S, Phi, workspace memory, Green's-function
+ * output buffers) is a device pointer on the current HIP device.  The library
+ * never takes ownership of caller memory.  Plans own their Green's-function
+ * spectrum, twiddle tables and one default workspace.
+ *
+ * Streams.  Solve calls only enqueue work on the given stream and return
+ * without synchronising; the caller keeps S and Phi alive until the stream has
+ * passed that point.  Plan creation and destruction are synchronous.
+ *
+ * Errors.  Every call returns a pspfft_status.  Argument checks happen before
+ * any work is enqueued; a failed check leaves nothing enqueued and nothing
+ * allocated.  A failed kernel launch returns PSPFFT_ERR_DEVICE.
+ *
+ * Supported sizes.  Each of nx, ny, nz must be 2^a * o with o in {1, 3, 5, 9}
+ * and n >= 8 (o = 1), 10 (o = 5), 12 (o = 3) or 18 (o = 9); n <= 2048 in FP32
+ * and n <= 1152 in FP64.  Other sizes return PSPFFT_ERR_UNSUPPORTED_SIZE.
+ */
+#ifndef PSPFFT_H
+#define PSPFFT_H
+
+#include <stddef.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pspfft_plan_s *pspfft_plan_t;           /* immutable after creation */
+typedef struct pspfft_workspace_s *pspfft_workspace_t; /* mutable per-in-flight-solve buffer */
+
+typedef enum {
+    PSPFFT_OK = 0,
+    PSPFFT_ERR_INVALID_ARGUMENT = 1, /* null pointer, non-finite or non-positive h, bad count */
+    PSPFFT_ERR_UNSUPPORTED_SIZE = 2, /* mesh size outside the supported set */
+    PSPFFT_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed; nothing leaked */
+    PSPFFT_ERR_DEVICE = 4,           /* a HIP call or kernel launch failed */
+    PSPFFT_ERR_NOT_IMPLEMENTED = 5
+} pspfft_status;
+
+/* Arithmetic precision of a plan; stands in for the paper's compile-time real
+ * kind KR (Sec. 3.2).  FP32 plans compute every pass in FP32 with twiddles and
+ * Green's-function spectrum generated in FP64 and rounded once. */
+typedef enum { PSPFFT_FP32 = 0, PSPFFT_FP64 = 1 } pspfft_precision;
+
+/* The five passes of one solve (Sec. 2.2.2: x transforms, transpose, y
+ * transforms, transpose, z transforms with the multiply by the Green's-function
+ * transform, then the reverse sequence).  On one GPU the transposes become
+ * strided column passes over the workspace. */
+typedef enum {
+    PSPFFT_PASS_X_FWD = 0,  /* zero-padded real-to-complex transforms along x     */
+    PSPFFT_PASS_Y_FWD = 1,  /* transforms along y, upper half of the input zero   */
+    PSPFFT_PASS_Z_CONV = 2, /* forward z transform, multiply by G~, inverse z      */
+    PSPFFT_PASS_Y_INV = 3,  /* inverse transforms along y, only y < ny kept        */
+    PSPFFT_PASS_X_INV = 4   /* inverse complex-to-real along x, only x < nx kept   */
+} pspfft_pass;
+
+/*
+ * Create a solver for an nx x ny x nz mesh with spacings h[0..2] = (hx, hy, hz)
+ * (Sec. 3.2, Create: CellWidth and nTotalCells; the communicator has no analogue
+ * on one GPU).  Computes the transform of the doubled Green's function
+ * (Eq. (greens_function)) in FP64 on the device, scales it by
+ * 1/((2nx)(2ny)(2nz)) and keeps it resident in the plan's precision.
+ * Synchronous.  *out receives the plan on success and is untouched on failure.
+ */
+pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspfft_precision prec,
+                                 pspfft_plan_t *out);
+
+/* Release a plan and everything it owns (Sec. 3.2, Destroy).  Synchronises the
+ * device first.  NULL returns PSPFFT_ERR_INVALID_ARGUMENT. */
+pspfft_status pspfft_destroy(pspfft_plan_t plan);
+
+/*
+ * Phi = potential of S (Sec. 3.2, Solve).  S and Phi: device arrays of nx*ny*nz
+ * reals in the plan's precision, layout as above.  S == Phi is allowed (the
+ * paper overwrites the source with the potential).  Uses the plan's default
+ * workspace, so solves on one plan serialise on that workspace: concurrent
+ * solves need a workspace each (pspfft_solve_ws).  Enqueues five kernels.
+ */
+pspfft_status pspfft_solve(pspfft_plan_t plan, const void *S, void *Phi, hipStream_t stream);
+
+/* Allocate a workspace for one in-flight solve of this plan
+ * (pspfft_workspace_bytes bytes of device memory, owned by the workspace). */
+pspfft_status pspfft_workspace_create(pspfft_plan_t plan, pspfft_workspace_t *out);
+
+/* Wrap caller-owned device memory (at least pspfft_workspace_bytes bytes,
+ * 256-byte aligned) as a workspace.  The memory stays the caller's. */
+pspfft_status pspfft_workspace_wrap(pspfft_plan_t plan, void *memory, size_t bytes,
+                                    pspfft_workspace_t *out);
+
+/* Release a workspace handle (and its memory unless it was wrapped). */
+pspfft_status pspfft_workspace_destroy(pspfft_workspace_t ws);
+
+/* As pspfft_solve, with an explicit workspace created for the same plan. */
+pspfft_status pspfft_solve_ws(pspfft_plan_t plan, pspfft_workspace_t ws, const void *S, void *Phi,
+                              hipStream_t stream);
+
+/*
+ * Solve `count` independent problems.  plans[i], ws[i], S[i], Phi[i] describe
+ * problem i; plans may differ in size and precision; each ws[i] must belong to
+ * plans[i] and be distinct from every other ws[j].  Each pass is issued as one
+ * launch per group of problems sharing a precision and a radix family (at most
+ * 32 problems per launch), so a batch of mixed sizes costs a handful of launches
+ * per pass.  Results do not depend on what else is in the batch: every problem
+ * is cut into the same tiles whatever its neighbours.
+ */
+pspfft_status pspfft_solve_batched(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
+                                   const void *const *S, void *const *Phi, hipStream_t stream);
+
+/*
+ * Run a single pass of the solve for `count` problems (same argument meaning as
+ * pspfft_solve_batched).  Running PSPFFT_PASS_X_FWD .. PSPFFT_PASS_X_INV in
+ * order on the same stream equals pspfft_solve_batched.  Used by schedulers that
+ * let problems join at pass granularity, and to time passes separately.  S is
+ * read only by PSPFFT_PASS_X_FWD and Phi written only by PSPFFT_PASS_X_INV.
+ */
+pspfft_status pspfft_pass_batched(pspfft_pass pass, int count, const pspfft_plan_t *plans,
+                                  const pspfft_workspace_t *ws, const void *const *S, void *const *Phi,
+                                  hipStream_t stream);
+
+/* Device bytes a plan keeps resident (Green's-function spectrum, twiddles,
+ * plan tables, default workspace).  0 for NULL. */
+size_t pspfft_plan_bytes(pspfft_plan_t plan);
+
+/* Bytes of one workspace: 2 ny nz (nx + 1) complex values of the precision.
+ * 0 for an unsupported size. */
+size_t pspfft_workspace_bytes(int nx, int ny, int nz, pspfft_precision prec);
+
+/* Algorithmic HBM bytes one pass moves for one problem of this plan: the
+ * values it must read and write once each (zero halves never touched).  Used
+ * for effective-bandwidth reports.  0 for NULL or an unknown pass. */
+size_t pspfft_pass_bytes(pspfft_plan_t plan, pspfft_pass pass);
+
+/* Size, spacings and precision of a plan (any output pointer may be NULL). */
+pspfft_status pspfft_plan_info(pspfft_plan_t plan, int dims[3], double h[3], pspfft_precision *prec);
+
+/*
+ * Copy the plan's Green's-function spectrum to `dst` (device memory of
+ * (nz+1)(ny+1)(nx+1) reals in the plan's precision): dst[(kz*(ny+1) + ky)*(nx+1)
+ * + kx] = DFT(doubled G)(kx, ky, kz) / ((2nx)(2ny)(2nz)) for kx <= nx, ky <= ny,
+ * kz <= nz.  The transform is real and even in each axis, so this octant holds
+ * all of it.  Enqueued on `stream`.
+ */
+pspfft_status pspfft_plan_green(pspfft_plan_t plan, void *dst, hipStream_t stream);
+
+/* Static, human-readable description of a status code. */
+const char *pspfft_status_string(pspfft_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSPFFT_H */

@@ -53,6 +53,7 @@ def _load():
     lib.oracle_dft_1d.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int]
     lib.oracle_fft_1d.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int]
     lib.oracle_fft_3d.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
+    lib.oracle_fft_axis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int]
     lib.oracle_green_value.argtypes = [ctypes.c_long, ctypes.c_long, ctypes.c_long, dp]
     lib.oracle_green_value.restype = ctypes.c_double
     lib.oracle_green_doubled.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
@@ -103,6 +104,15 @@ def fft_3d(a: np.ndarray, sign: int = -1) -> np.ndarray:
     a = np.array(a, dtype=np.complex128, order="C", copy=True)
     nz, ny, nx = a.shape
     _load().oracle_fft_3d(nx, ny, nz, _dptr(a.view(np.float64)), sign)
+    return a
+
+
+def fft_axis(a: np.ndarray, axis: int, sign: int = -1) -> np.ndarray:
+    """1D transforms along ``axis`` (0 = x, the last array axis; 2 = z, the first) of a
+    complex (nz, ny, nx) array; returns a new array."""
+    a = np.array(a, dtype=np.complex128, order="C", copy=True)
+    nz, ny, nx = a.shape
+    _load().oracle_fft_axis(nx, ny, nz, _dptr(a.view(np.float64)), int(axis), sign)
     return a
 
 

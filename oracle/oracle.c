@@ -11,6 +11,7 @@
  *   - oracle_dft_1d     textbook O(L^2) discrete Fourier transform.
  *   - oracle_fft_1d     naive recursive mixed-radix (any prime factor) FFT,
  *                       decimation in time, no blocking or reordering tricks.
+ *   - oracle_fft_axis   1D transforms along one axis of a 3D array.
  *   - oracle_fft_3d     3D transform as three sets of 1D transforms (Sec. 2.2.2).
  *   - oracle_green_value     the discrete Green's function, Eq. (greens2) at
  *                            integer index offsets, with the self-cell value of
@@ -159,6 +160,11 @@ static void fft_axis(cplx *a, int nx, int ny, int nz, int axis, int sign) {
         free(y);
     }
     free(w);
+}
+
+/* In-place transform of one axis (0 = x, 1 = y, 2 = z) of a complex [nz][ny][nx] array. */
+void oracle_fft_axis(int nx, int ny, int nz, double *a, int axis, int sign) {
+    fft_axis((cplx *)a, nx, ny, nz, axis, sign);
 }
 
 void oracle_fft_3d(int nx, int ny, int nz, double *a, int sign) {

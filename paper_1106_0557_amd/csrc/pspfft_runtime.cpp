@@ -1,0 +1,541 @@
+// pspfft_runtime.cpp -- host side of the C ABI declared in include/pspfft.h:
+// size validation, per-axis stage plans and twiddle tables, the resident
+// Green's-function spectrum (computed once at plan creation, Sec. 2.2.2), default
+// and caller workspaces, and grouped launches of the five passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/pspfft.h"
+#include "internal.h"
+
+using pspfft::AxisPlan;
+using pspfft::DevPlan;
+using pspfft::LaunchArgs;
+using pspfft::ProbArg;
+
+struct pspfft_plan_s {
+    int n[3];
+    double h[3];
+    pspfft_precision prec;
+    DevPlan host;            // copy of the device plan (device pointers inside)
+    DevPlan *dev = nullptr;  // device copy read by the kernels
+    void *tw[3] = {nullptr, nullptr, nullptr};
+    void *G = nullptr, *Gn = nullptr;
+    pspfft_workspace_t ws = nullptr;  // default workspace
+    size_t bytes = 0;
+    int device = 0;
+};
+
+struct pspfft_workspace_s {
+    pspfft_plan_t plan;
+    void *mem;
+    bool owned;
+    void *W;
+    void *Wn;
+    size_t bytes;
+};
+
+namespace {
+
+int log_level() {
+    static int level = -1;
+    if (level < 0) {
+        const char *e = std::getenv("PSPFFT_LOG");
+        level = 0;
+        if (e) {
+            if (!std::strcmp(e, "warn")) level = 1;
+            else if (!std::strcmp(e, "info1")) level = 2;
+            else if (!std::strcmp(e, "info2")) level = 3;
+        }
+    }
+    return level;
+}
+
+#define PSPFFT_LOG(lvl, ...)                      \
+    do {                                          \
+        if (log_level() >= (lvl)) {               \
+            std::fprintf(stderr, "[pspfft] ");    \
+            std::fprintf(stderr, __VA_ARGS__);    \
+            std::fprintf(stderr, "\n");           \
+        }                                         \
+    } while (0)
+
+size_t real_size(pspfft_precision p) { return p == PSPFFT_FP32 ? 4 : 8; }
+size_t cplx_size(pspfft_precision p) { return 2 * real_size(p); }
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Radix family of a transform length L = 2n: the odd part o of L selects E, the
+// elements each thread owns; every stage radix divides E.
+int family_of(int n) {
+    if (n < 1) return 0;
+    int m = n;
+    while (m % 2 == 0) m /= 2;
+    int E = 0;
+    if (m == 1) E = 16;
+    else if (m == 3) E = 24;
+    else if (m == 5) E = 20;
+    else if (m == 9) E = 36;
+    else return 0;
+    const int L = 2 * n;
+    if (L < E || L % E != 0) return 0;
+    return E;
+}
+
+int max_n(pspfft_precision p) { return p == PSPFFT_FP32 ? 2048 : 1152; }
+
+bool size_ok(int n, pspfft_precision p) { return n >= 1 && n <= max_n(p) && family_of(n) != 0; }
+
+// cos and sin of 2 pi j / M in double precision, folded into [0, pi/4] first.
+void turn(long j, long M, double &c, double &s) {
+    j %= M;
+    if (j < 0) j += M;
+    long num = j, den = M;
+    bool neg_s = false, neg_c = false, swap = false;
+    if (2 * num > den) { num = den - num; neg_s = true; }
+    if (4 * num > den) { num = den - 2 * num; den *= 2; neg_c = true; }
+    if (8 * num > den) { num = den - 4 * num; den *= 4; swap = true; }
+    const double x = 2.0 * M_PI * static_cast<double>(num) / static_cast<double>(den);
+    c = std::cos(x);
+    s = std::sin(x);
+    if (swap) std::swap(c, s);
+    if (neg_c) c = -c;
+    if (neg_s) s = -s;
+}
+
+// Stage plan and FP64 twiddles of one axis.
+bool build_axis(int n, AxisPlan &ax, std::vector<std::complex<double>> &tw) {
+    const int E = family_of(n);
+    if (!E) return false;
+    std::memset(&ax, 0, sizeof(ax));
+    ax.n = n;
+    ax.L = 2 * n;
+    ax.E = E;
+    ax.NB = ax.L / E;
+    int rem = ax.L, Ns = 1, s = 0;
+    tw.clear();
+    while (rem > 1) {
+        if (s >= pspfft::kMaxStages) return false;
+        const int R = std::gcd(E, rem);
+        if (R <= 1) return false;
+        ax.R[s] = R;
+        ax.Ns[s] = Ns;
+        ax.magic[s] = Ns > 1 ? static_cast<uint32_t>((uint64_t(1) << 32) / Ns + 1) : 0u;
+        if (Ns > 1) {  // verify the multiply-high division for every index used
+            for (uint32_t b = 0; b < static_cast<uint32_t>(ax.L); ++b) {
+                const uint32_t q = static_cast<uint32_t>((uint64_t(b) * ax.magic[s]) >> 32);
+                if (q != b / static_cast<uint32_t>(Ns)) return false;
+            }
+        }
+        ax.twoff[s] = static_cast<int>(tw.size());
+        for (int k = 0; k < Ns; ++k)
+            for (int r = 1; r < R; ++r) {
+                double c, sn;
+                turn(-static_cast<long>(r) * k, static_cast<long>(Ns) * R, c, sn);
+                tw.emplace_back(c, sn);
+            }
+        Ns *= R;
+        rem /= R;
+        ++s;
+    }
+    ax.nst = s;
+    if (tw.empty()) tw.emplace_back(1.0, 0.0);  // keep a valid pointer for one-stage lines
+    return Ns == ax.L;
+}
+
+// cos(pi j / n), j < 2n, for the even-extension transform of G.
+std::vector<double> cos_table(int n) {
+    std::vector<double> t(2 * n);
+    for (int j = 0; j < 2 * n; ++j) {
+        double c, s;
+        turn(j, 2L * n, c, s);
+        t[j] = c;
+    }
+    return t;
+}
+
+template <typename F>
+struct Guard {
+    F f;
+    bool armed = true;
+    ~Guard() {
+        if (armed) f();
+    }
+};
+template <typename F>
+Guard<F> make_guard(F f) { return Guard<F>{f}; }
+
+pspfft_status alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return PSPFFT_ERR_OUT_OF_MEMORY;
+    }
+    return PSPFFT_OK;
+}
+
+size_t ws_bytes(const int n[3], pspfft_precision prec) {
+    const size_t c = cplx_size(prec);
+    const size_t main = static_cast<size_t>(n[2]) * 2 * n[1] * n[0] * c;
+    const size_t nyq = static_cast<size_t>(n[2]) * 2 * n[1] * c;
+    return round_up(main, 256) + round_up(nyq, 256);
+}
+
+void ws_split(pspfft_workspace_t w, const int n[3], pspfft_precision prec) {
+    const size_t c = cplx_size(prec);
+    const size_t main = static_cast<size_t>(n[2]) * 2 * n[1] * n[0] * c;
+    w->W = w->mem;
+    w->Wn = static_cast<char *>(w->mem) + round_up(main, 256);
+}
+
+void destroy_plan(pspfft_plan_t p) {
+    if (!p) return;
+    if (p->ws) {
+        if (p->ws->owned && p->ws->mem) (void)hipFree(p->ws->mem);
+        delete p->ws;
+    }
+    for (auto &t : p->tw)
+        if (t) (void)hipFree(t);
+    if (p->G) (void)hipFree(p->G);
+    if (p->Gn) (void)hipFree(p->Gn);
+    if (p->dev) (void)hipFree(p->dev);
+    delete p;
+}
+
+// Lines (main, Nyquist) that a pass processes for one problem.
+void pass_lines(int mode, const int n[3], long &main, long &nyq) {
+    const long nx = n[0], ny = n[1], nz = n[2];
+    switch (mode) {
+        case pspfft::X_FWD:
+        case pspfft::X_INV: main = ny * nz; nyq = 0; break;
+        case pspfft::Y_FWD:
+        case pspfft::Y_INV: main = nz * nx; nyq = nz; break;
+        default: main = 2 * ny * nx; nyq = 2 * ny; break;
+    }
+}
+
+pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
+                       const void *const *S, void *const *Phi, hipStream_t stream) {
+    if (count < 0) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (count == 0) return PSPFFT_OK;
+    if (!plans || !ws) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (mode == pspfft::X_FWD && !S) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (mode == pspfft::X_INV && !Phi) return PSPFFT_ERR_INVALID_ARGUMENT;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !ws[i] || ws[i]->plan != plans[i]) return PSPFFT_ERR_INVALID_ARGUMENT;
+        if (mode == pspfft::X_FWD && !S[i]) return PSPFFT_ERR_INVALID_ARGUMENT;
+        if (mode == pspfft::X_INV && !Phi[i]) return PSPFFT_ERR_INVALID_ARGUMENT;
+    }
+    const int axis = pspfft::pass_axis(mode);
+    // group problems by (precision, radix family): one kernel per group
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int i = 0; i < count; ++i) groups[{static_cast<int>(plans[i]->prec), plans[i]->host.ax[axis].E}].push_back(i);
+    for (auto &kv : groups) {
+        const int prec = kv.first.first, E = kv.first.second;
+        const auto &idx = kv.second;
+        const int tile_target = prec == 0 ? 16 : 8;  // 128-byte rows of complex values
+        const int bmax = pspfft::max_block(prec, E);
+        const size_t csz = prec == 0 ? 8 : 16;
+        for (size_t c0 = 0; c0 < idx.size(); c0 += pspfft::kMaxProblems) {
+            const size_t c1 = std::min(idx.size(), c0 + pspfft::kMaxProblems);
+            int block = 0, nbmax = 1;
+            for (size_t j = c0; j < c1; ++j) {
+                const int NB = plans[idx[j]]->host.ax[axis].NB;
+                nbmax = std::max(nbmax, NB);
+                block = std::max(block, tile_target * NB);
+            }
+            block = std::min(std::max(block, 64), bmax);
+            while (block > nbmax && static_cast<size_t>(block) * E * csz > 160 * 1024) block /= 2;
+            if (block < nbmax) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+            const size_t lds = static_cast<size_t>(block) * E * csz;
+            LaunchArgs args;
+            std::memset(&args, 0, sizeof(args));
+            args.count = static_cast<int>(c1 - c0);
+            long wg = 0;
+            for (size_t j = c0; j < c1; ++j) {
+                const int i = idx[j];
+                const pspfft_plan_t pl = plans[i];
+                const int tile = block / pl->host.ax[axis].NB;
+                long lm, ln;
+                pass_lines(mode, pl->n, lm, ln);
+                ProbArg &a = args.p[j - c0];
+                a.plan = pl->dev;
+                a.S = S ? S[i] : nullptr;
+                a.Phi = Phi ? Phi[i] : nullptr;
+                a.W = ws[i]->W;
+                a.Wn = ws[i]->Wn;
+                a.wg_begin = static_cast<int>(wg);
+                const long wm = (lm + tile - 1) / tile, wn = (ln + tile - 1) / tile;
+                a.wg_main = static_cast<int>(wm);
+                wg += wm + wn;
+            }
+            if (wg > 0x7fffffffL) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+            PSPFFT_LOG(3, "pass %d prec %d E %d: %d problems, %ld workgroups of %d threads, %zu B LDS", mode, prec, E,
+                       args.count, wg, block, lds);
+            if (pspfft::launch_pass(mode, prec, E, args, static_cast<int>(wg), block, lds, stream) != hipSuccess)
+                return PSPFFT_ERR_DEVICE;
+        }
+    }
+    return PSPFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pspfft_status_string(pspfft_status s) {
+    switch (s) {
+        case PSPFFT_OK: return "success";
+        case PSPFFT_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case PSPFFT_ERR_UNSUPPORTED_SIZE: return "unsupported mesh size";
+        case PSPFFT_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case PSPFFT_ERR_DEVICE: return "HIP device error";
+        case PSPFFT_ERR_NOT_IMPLEMENTED: return "not implemented";
+    }
+    return "unknown status";
+}
+
+size_t pspfft_workspace_bytes(int nx, int ny, int nz, pspfft_precision prec) {
+    if (prec != PSPFFT_FP32 && prec != PSPFFT_FP64) return 0;
+    if (!size_ok(nx, prec) || !size_ok(ny, prec) || !size_ok(nz, prec)) return 0;
+    const int n[3] = {nx, ny, nz};
+    return ws_bytes(n, prec);
+}
+
+pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspfft_precision prec,
+                                 pspfft_plan_t *out) {
+    if (!out || !h) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (prec != PSPFFT_FP32 && prec != PSPFFT_FP64) return PSPFFT_ERR_INVALID_ARGUMENT;
+    for (int a = 0; a < 3; ++a)
+        if (!(std::isfinite(h[a]) && h[a] > 0.0)) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (nx < 1 || ny < 1 || nz < 1) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (!size_ok(nx, prec) || !size_ok(ny, prec) || !size_ok(nz, prec)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+
+    pspfft_plan_t p = new (std::nothrow) pspfft_plan_s();
+    if (!p) return PSPFFT_ERR_OUT_OF_MEMORY;
+    auto guard = make_guard([&] { destroy_plan(p); });
+    p->n[0] = nx;
+    p->n[1] = ny;
+    p->n[2] = nz;
+    for (int a = 0; a < 3; ++a) p->h[a] = h[a];
+    p->prec = prec;
+    if (hipGetDevice(&p->device) != hipSuccess) return PSPFFT_ERR_DEVICE;
+    const size_t rs = real_size(prec), cs = cplx_size(prec);
+    std::memset(&p->host, 0, sizeof(p->host));
+    p->host.nx = nx;
+    p->host.ny = ny;
+    p->host.nz = nz;
+    p->host.prec = prec == PSPFFT_FP32 ? 0 : 1;
+    size_t bytes = 0;
+
+    // stage plans and twiddle tables (FP64, rounded once to the plan precision)
+    for (int a = 0; a < 3; ++a) {
+        std::vector<std::complex<double>> tw;
+        if (!build_axis(p->n[a], p->host.ax[a], tw)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+        const size_t tb = tw.size() * cs;
+        pspfft_status st = alloc(&p->tw[a], tb);
+        if (st != PSPFFT_OK) return st;
+        std::vector<unsigned char> buf(tb);
+        for (size_t i = 0; i < tw.size(); ++i) {
+            if (prec == PSPFFT_FP32) {
+                const float v[2] = {static_cast<float>(tw[i].real()), static_cast<float>(tw[i].imag())};
+                std::memcpy(&buf[i * cs], v, sizeof(v));
+            } else {
+                const double v[2] = {tw[i].real(), tw[i].imag()};
+                std::memcpy(&buf[i * cs], v, sizeof(v));
+            }
+        }
+        if (hipMemcpy(p->tw[a], buf.data(), tb, hipMemcpyHostToDevice) != hipSuccess) return PSPFFT_ERR_DEVICE;
+        p->host.ax[a].tw = p->tw[a];
+        bytes += tb;
+    }
+
+    // Green's-function spectrum, computed once in FP64 and kept (Sec. 2.2.2)
+    const size_t oct = static_cast<size_t>(nx + 1) * (ny + 1) * (nz + 1);
+    const size_t gmain = static_cast<size_t>(nz + 1) * (ny + 1) * nx * rs;
+    const size_t gnyq = static_cast<size_t>(nz + 1) * (ny + 1) * rs;
+    pspfft_status st;
+    if ((st = alloc(&p->G, gmain)) != PSPFFT_OK) return st;
+    if ((st = alloc(&p->Gn, gnyq)) != PSPFFT_OK) return st;
+    bytes += gmain + gnyq;
+    {
+        void *a = nullptr, *b = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;
+        hipStream_t s = nullptr;
+        auto tmp = make_guard([&] {
+            if (s) (void)hipStreamDestroy(s);
+            for (void *q : {a, b, cx, cy, cz})
+                if (q) (void)hipFree(q);
+        });
+        if ((st = alloc(&a, oct * sizeof(double))) != PSPFFT_OK) return st;
+        if ((st = alloc(&b, oct * sizeof(double))) != PSPFFT_OK) return st;
+        const std::vector<double> tx = cos_table(nx), ty = cos_table(ny), tz = cos_table(nz);
+        if ((st = alloc(&cx, tx.size() * sizeof(double))) != PSPFFT_OK) return st;
+        if ((st = alloc(&cy, ty.size() * sizeof(double))) != PSPFFT_OK) return st;
+        if ((st = alloc(&cz, tz.size() * sizeof(double))) != PSPFFT_OK) return st;
+        if (hipMemcpy(cx, tx.data(), tx.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(cy, ty.data(), ty.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(cz, tz.data(), tz.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+            return PSPFFT_ERR_DEVICE;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PSPFFT_ERR_DEVICE;
+        if (pspfft::green_spectrum(nx, ny, nz, p->h, p->host.prec, static_cast<double *>(a), static_cast<double *>(b),
+                                   static_cast<const double *>(cx), static_cast<const double *>(cy),
+                                   static_cast<const double *>(cz), p->G, p->Gn, s) != hipSuccess)
+            return PSPFFT_ERR_DEVICE;
+        if (hipStreamSynchronize(s) != hipSuccess) return PSPFFT_ERR_DEVICE;
+    }
+    p->host.G = p->G;
+    p->host.Gn = p->Gn;
+
+    void *dv = nullptr;
+    if ((st = alloc(&dv, sizeof(DevPlan))) != PSPFFT_OK) return st;
+    p->dev = static_cast<DevPlan *>(dv);
+    if (hipMemcpy(p->dev, &p->host, sizeof(DevPlan), hipMemcpyHostToDevice) != hipSuccess) return PSPFFT_ERR_DEVICE;
+    bytes += sizeof(DevPlan);
+
+    // default workspace
+    p->ws = new (std::nothrow) pspfft_workspace_s();
+    if (!p->ws) return PSPFFT_ERR_OUT_OF_MEMORY;
+    p->ws->plan = p;
+    p->ws->owned = true;
+    p->ws->mem = nullptr;
+    p->ws->bytes = ws_bytes(p->n, prec);
+    if ((st = alloc(&p->ws->mem, p->ws->bytes)) != PSPFFT_OK) return st;
+    ws_split(p->ws, p->n, prec);
+    bytes += p->ws->bytes;
+    p->bytes = bytes;
+
+    PSPFFT_LOG(2, "plan %dx%dx%d %s: %zu bytes resident", nx, ny, nz, prec == PSPFFT_FP32 ? "fp32" : "fp64", bytes);
+    guard.armed = false;
+    *out = p;
+    return PSPFFT_OK;
+}
+
+pspfft_status pspfft_destroy(pspfft_plan_t plan) {
+    if (!plan) return PSPFFT_ERR_INVALID_ARGUMENT;
+    (void)hipDeviceSynchronize();
+    destroy_plan(plan);
+    return PSPFFT_OK;
+}
+
+pspfft_status pspfft_workspace_create(pspfft_plan_t plan, pspfft_workspace_t *out) {
+    if (!plan || !out) return PSPFFT_ERR_INVALID_ARGUMENT;
+    pspfft_workspace_t w = new (std::nothrow) pspfft_workspace_s();
+    if (!w) return PSPFFT_ERR_OUT_OF_MEMORY;
+    w->plan = plan;
+    w->owned = true;
+    w->bytes = ws_bytes(plan->n, plan->prec);
+    pspfft_status st = alloc(&w->mem, w->bytes);
+    if (st != PSPFFT_OK) {
+        delete w;
+        return st;
+    }
+    ws_split(w, plan->n, plan->prec);
+    *out = w;
+    return PSPFFT_OK;
+}
+
+pspfft_status pspfft_workspace_wrap(pspfft_plan_t plan, void *memory, size_t bytes, pspfft_workspace_t *out) {
+    if (!plan || !memory || !out) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (bytes < ws_bytes(plan->n, plan->prec)) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (reinterpret_cast<uintptr_t>(memory) % 256 != 0) return PSPFFT_ERR_INVALID_ARGUMENT;
+    pspfft_workspace_t w = new (std::nothrow) pspfft_workspace_s();
+    if (!w) return PSPFFT_ERR_OUT_OF_MEMORY;
+    w->plan = plan;
+    w->owned = false;
+    w->mem = memory;
+    w->bytes = bytes;
+    ws_split(w, plan->n, plan->prec);
+    *out = w;
+    return PSPFFT_OK;
+}
+
+pspfft_status pspfft_workspace_destroy(pspfft_workspace_t ws) {
+    if (!ws) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (ws->plan && ws == ws->plan->ws) return PSPFFT_ERR_INVALID_ARGUMENT;  // owned by its plan
+    if (ws->owned && ws->mem) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ws->mem);
+    }
+    delete ws;
+    return PSPFFT_OK;
+}
+
+pspfft_status pspfft_pass_batched(pspfft_pass pass, int count, const pspfft_plan_t *plans,
+                                  const pspfft_workspace_t *ws, const void *const *S, void *const *Phi,
+                                  hipStream_t stream) {
+    if (pass < PSPFFT_PASS_X_FWD || pass > PSPFFT_PASS_X_INV) return PSPFFT_ERR_INVALID_ARGUMENT;
+    return run_pass(static_cast<int>(pass), count, plans, ws, S, Phi, stream);
+}
+
+pspfft_status pspfft_solve_batched(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
+                                   const void *const *S, void *const *Phi, hipStream_t stream) {
+    if (count < 0 || (count > 0 && (!plans || !ws || !S || !Phi))) return PSPFFT_ERR_INVALID_ARGUMENT;
+    for (int i = 0; i < count; ++i)
+        for (int j = i + 1; j < count; ++j)
+            if (ws[i] == ws[j]) return PSPFFT_ERR_INVALID_ARGUMENT;
+    for (int mode = pspfft::X_FWD; mode <= pspfft::X_INV; ++mode) {
+        pspfft_status st = run_pass(mode, count, plans, ws, S, Phi, stream);
+        if (st != PSPFFT_OK) return st;
+    }
+    return PSPFFT_OK;
+}
+
+pspfft_status pspfft_solve_ws(pspfft_plan_t plan, pspfft_workspace_t ws, const void *S, void *Phi,
+                              hipStream_t stream) {
+    if (!plan || !ws || !S || !Phi) return PSPFFT_ERR_INVALID_ARGUMENT;
+    return pspfft_solve_batched(1, &plan, &ws, &S, &Phi, stream);
+}
+
+pspfft_status pspfft_solve(pspfft_plan_t plan, const void *S, void *Phi, hipStream_t stream) {
+    if (!plan || !S || !Phi) return PSPFFT_ERR_INVALID_ARGUMENT;
+    return pspfft_solve_ws(plan, plan->ws, S, Phi, stream);
+}
+
+size_t pspfft_plan_bytes(pspfft_plan_t plan) { return plan ? plan->bytes : 0; }
+
+size_t pspfft_pass_bytes(pspfft_plan_t plan, pspfft_pass pass) {
+    if (!plan) return 0;
+    const size_t r = real_size(plan->prec), c = cplx_size(plan->prec);
+    const size_t nx = plan->n[0], ny = plan->n[1], nz = plan->n[2];
+    const size_t half = ny * nz * (nx + 1) * c;  // spectrum rows y < ny (kx <= nx)
+    const size_t full = 2 * half;                // all 2ny rows
+    switch (pass) {
+        case PSPFFT_PASS_X_FWD: return nx * ny * nz * r + half;
+        case PSPFFT_PASS_Y_FWD: return half + full;
+        case PSPFFT_PASS_Z_CONV: return 2 * full + (nx + 1) * (ny + 1) * (nz + 1) * r;
+        case PSPFFT_PASS_Y_INV: return full + half;
+        case PSPFFT_PASS_X_INV: return half + nx * ny * nz * r;
+    }
+    return 0;
+}
+
+pspfft_status pspfft_plan_info(pspfft_plan_t plan, int dims[3], double h[3], pspfft_precision *prec) {
+    if (!plan) return PSPFFT_ERR_INVALID_ARGUMENT;
+    for (int a = 0; a < 3; ++a) {
+        if (dims) dims[a] = plan->n[a];
+        if (h) h[a] = plan->h[a];
+    }
+    if (prec) *prec = plan->prec;
+    return PSPFFT_OK;
+}
+
+pspfft_status pspfft_plan_green(pspfft_plan_t plan, void *dst, hipStream_t stream) {
+    if (!plan || !dst) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (pspfft::green_export(plan->n[0], plan->n[1], plan->n[2], plan->host.prec, plan->G, plan->Gn, dst, stream) !=
+        hipSuccess)
+        return PSPFFT_ERR_DEVICE;
+    return PSPFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,291 @@
+"""Parity of the HIP path against the FP64 CPU oracle (needs a gfx950 GPU).
+
+Bars: FP64 <= 1e-12 relative L2 and relative max against the oracle; FP32 <=
+1e-5 relative L2 against the FP64 oracle (max error reported).  Integer-like
+checks (batched == single) are bit-exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import norms
+from paper_1106_0557_amd import sources
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_1106_0557_amd  # noqa: F401
+    from paper_1106_0557_amd import _lib
+
+    _lib.load()
+    yield
+
+
+def gpu_solve(n, h, S, dtype):
+    from paper_1106_0557_amd import Plan
+
+    plan = Plan(*n, h=h, dtype=dtype)
+    phi = plan.solve(torch.as_tensor(S).to("cuda", dtype))
+    torch.cuda.synchronize()
+    out = phi.double().cpu().numpy()
+    plan.close()
+    return out
+
+
+# ---------------------------------------------------------------- spectrum --
+
+@pytest.mark.parametrize("n,h", [((16, 16, 16), (1 / 16,) * 3), ((12, 10, 16), (0.3, 0.2, 0.5)),
+                                 ((24, 18, 20), (0.05, 0.07, 0.06)), ((36, 8, 40), (1.0, 1.0, 2.0))])
+def test_green_spectrum_matches_oracle(n, h):
+    from paper_1106_0557_amd import Plan
+
+    say(f"[spectrum] n={n} h={h}")
+    want, imag_max, abs_max = oracle.green_hat_octant(n, h)
+    for dtype, tol in ((torch.float64, FP64_TOL), (torch.float32, 1e-7)):
+        plan = Plan(*n, h=h, dtype=dtype)
+        got = plan.green().double().cpu().numpy()
+        plan.close()
+        err = np.abs(got - want).max() / abs_max
+        say(f"  {dtype}: max err / max|G~| = {err:.3e}")
+        assert err <= tol
+
+
+# ---------------------------------------------------------- per-pass stages --
+
+def _workspace_views(plan, mem):
+    nx, ny, nz = plan.n
+    csz = 16 if plan.dtype == torch.float64 else 8
+    main = nz * 2 * ny * nx * csz
+    off = (main + 255) // 256 * 256
+    cdt = torch.complex128 if plan.dtype == torch.float64 else torch.complex64
+    W = mem[:main].view(cdt).view(nz, 2 * ny, nx)
+    Wn = mem[off:off + nz * 2 * ny * csz].view(cdt).view(nz, 2 * ny)
+    return W, Wn
+
+
+@pytest.mark.parametrize("n", [(24, 20, 16), (16, 36, 24), (40, 16, 18)])
+def test_each_pass_matches_oracle_stage(n):
+    """Run the passes one at a time and compare the workspace with the oracle's stages."""
+    from paper_1106_0557_amd import (PASS_X_FWD, PASS_Y_FWD, PASS_Z_CONV, PASS_Y_INV, PASS_X_INV, Plan,
+                                     Workspace, pass_batched)
+
+    say(f"[passes] n={n}")
+    nx, ny, nz = n
+    h = (0.3, 0.2, 0.5)
+    S = sources.random_field(n, seed=11).numpy()
+    plan = Plan(*n, h=h, dtype=torch.float64)
+    mem = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    ws = Workspace(plan, memory=mem)
+    W, Wn = _workspace_views(plan, mem)
+    Sd = torch.from_numpy(S).cuda()
+    Phi = torch.empty_like(Sd)
+
+    def spectrum_rows(A, zmax, ymax):
+        """Compare W (kx < nx) and Wn (kx = nx) with A[z<zmax, y<ymax, kx<=nx]."""
+        torch.cuda.synchronize()
+        got = W.cpu().numpy()[:zmax, :ymax, :]
+        gotn = Wn.cpu().numpy()[:zmax, :ymax]
+        ref = A[:zmax, :ymax, : nx + 1]
+        scale = np.abs(ref).max()
+        e1 = np.abs(got - ref[:, :, :nx]).max() / scale
+        e2 = np.abs(gotn - ref[:, :, nx]).max() / scale
+        return max(e1, e2)
+
+    A = np.zeros((2 * nz, 2 * ny, 2 * nx), complex)
+    A[:nz, :ny, :nx] = S
+    A = oracle.fft_axis(A, 0)
+    pass_batched(PASS_X_FWD, [ws], S=[Sd], Phi=[Phi])
+    e = spectrum_rows(A, nz, ny)
+    say(f"  x_fwd err {e:.2e}")
+    assert e <= FP64_TOL
+
+    A = oracle.fft_axis(A, 1)
+    pass_batched(PASS_Y_FWD, [ws], S=[Sd], Phi=[Phi])
+    e = spectrum_rows(A, nz, 2 * ny)
+    say(f"  y_fwd err {e:.2e}")
+    assert e <= FP64_TOL
+
+    g = oracle.green_doubled(n, h)
+    ghat = np.fft.fftn(g).real / g.size  # an independent transform of the doubled G
+    A[nz:] = 0.0  # the z pass reads only z < nz (the rest is zero padding)
+    A = oracle.fft_axis(oracle.fft_axis(A, 2) * ghat, 2, +1)
+    pass_batched(PASS_Z_CONV, [ws], S=[Sd], Phi=[Phi])
+    e = spectrum_rows(A, nz, 2 * ny)
+    say(f"  z_conv err {e:.2e}")
+    assert e <= FP64_TOL
+
+    A[nz:] = 0.0
+    A = oracle.fft_axis(A, 1, +1)
+    pass_batched(PASS_Y_INV, [ws], S=[Sd], Phi=[Phi])
+    e = spectrum_rows(A, nz, ny)
+    say(f"  y_inv err {e:.2e}")
+    assert e <= FP64_TOL
+
+    A[:, ny:] = 0.0
+    A = oracle.fft_axis(A, 0, +1)
+    pass_batched(PASS_X_INV, [ws], S=[Sd], Phi=[Phi])
+    torch.cuda.synchronize()
+    ref = A[:nz, :ny, :nx].real
+    e = norms.rel_max(Phi.cpu().numpy(), ref)
+    say(f"  x_inv err {e:.2e}")
+    assert e <= FP64_TOL
+    # and the whole thing equals the oracle solve
+    assert norms.rel_l2(Phi.cpu().numpy(), oracle.solve_fft(S, h)) <= FP64_TOL
+    ws.close()
+    plan.close()
+
+
+# ------------------------------------------------------------ whole solve --
+
+SIZES = [
+    (8, 8, 8), (16, 16, 16), (32, 32, 32), (24, 24, 24), (20, 20, 20), (36, 36, 36), (48, 32, 24),
+    (40, 12, 18), (10, 12, 16), (64, 48, 40), (96, 96, 96), (72, 18, 144),
+]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_solve_matches_oracle(n):
+    say(f"[solve] n={n}")
+    h = tuple(1.0 / v for v in n)
+    S = sources.random_field(n, seed=sum(n)).numpy()
+    ref = oracle.solve_fft(S, h)
+    got64 = gpu_solve(n, h, S, torch.float64)
+    r64 = norms.report(got64, ref)
+    got32 = gpu_solve(n, h, S, torch.float32)
+    r32 = norms.report(got32, ref)
+    say(f"  fp64 {r64}\n  fp32 {r32}")
+    assert r64["rel_l2"] <= FP64_TOL and r64["rel_max"] <= FP64_TOL
+    assert r32["rel_l2"] <= FP32_TOL
+
+
+def test_zero_source_gives_zero_potential():
+    say("[zero source]")
+    n = (24, 16, 20)
+    for dtype in (torch.float32, torch.float64):
+        got = gpu_solve(n, 0.1, np.zeros(n[::-1]), dtype)
+        assert np.all(got == 0.0)
+
+
+@pytest.mark.parametrize("c", [(0, 0, 0), (5, 3, 7), (15, 11, 9)])
+def test_impulse_response_is_green_function(c):
+    say(f"[impulse] c={c}")
+    n = (16, 12, 10)
+    h = (0.3, 0.2, 0.5)
+    S = np.zeros(n[::-1])
+    S[c[2], c[1], c[0]] = 1.0
+    got = gpu_solve(n, h, S, torch.float64)
+    want = np.empty_like(S)
+    for z in range(n[2]):
+        for y in range(n[1]):
+            for x in range(n[0]):
+                want[z, y, x] = oracle.green_value(abs(x - c[0]), abs(y - c[1]), abs(z - c[2]), h)
+    assert np.abs(got - want).max() <= FP64_TOL * np.abs(want).max()
+
+
+def test_config1_matches_full_direct_sum():
+    say("[config1] n=32 sphere vs direct sum")
+    n, h, S = sources.config1()
+    S = S.numpy()
+    want = oracle.direct(S, h)
+    got64 = gpu_solve((n,) * 3, h, S, torch.float64)
+    got32 = gpu_solve((n,) * 3, h, S, torch.float32)
+    r64, r32 = norms.report(got64, want), norms.report(got32, want)
+    say(f"  fp64 {r64}\n  fp32 {r32}")
+    assert r64["rel_l2"] <= FP64_TOL and r64["rel_max"] <= FP64_TOL
+    assert r32["rel_l2"] <= FP32_TOL
+
+
+def test_config2_spheroid_n128():
+    from oracle import closed_forms as cf
+
+    say("[config2] n=128 spheroid")
+    n, h, S = sources.config2()
+    S = S.numpy()
+    ref = oracle.solve_fft(S, h)
+    got64 = gpu_solve((n,) * 3, h, S, torch.float64)
+    got32 = gpu_solve((n,) * 3, h, S, torch.float32)
+    r64, r32 = norms.report(got64, ref), norms.report(got32, ref)
+    r32_64 = norms.report(got32, got64)
+    say(f"  fp64 vs oracle {r64}\n  fp32 vs oracle {r32}\n  fp32 vs gpu fp64 {r32_64}")
+    assert r64["rel_l2"] <= FP64_TOL and r64["rel_max"] <= FP64_TOL
+    assert r32["rel_l2"] <= FP32_TOL and r32_64["rel_l2"] <= FP32_TOL
+    x = (np.arange(n) + 0.5) * h - 0.5
+    analytic = cf.phi_spheroid(x[None, None, :], x[None, :, None], x[:, None, None], 0.3, 0.15, 1.0)
+    l1 = norms.l1(got64, analytic)
+    say(f"  L1 vs analytic spheroid: {l1:.3e}")
+    assert l1 < 5e-3
+
+
+def test_in_place_solve():
+    from paper_1106_0557_amd import Plan
+
+    say("[in place]")
+    n = (32, 24, 16)
+    S = sources.random_field(n, seed=3)
+    ref = oracle.solve_fft(S.numpy(), 0.1)
+    for dtype, tol in ((torch.float64, FP64_TOL), (torch.float32, FP32_TOL)):
+        plan = Plan(*n, h=0.1, dtype=dtype)
+        buf = S.to("cuda", dtype)
+        plan.solve(buf, out=buf)
+        torch.cuda.synchronize()
+        assert norms.rel_l2(buf.double().cpu().numpy(), ref) <= tol
+        plan.close()
+
+
+@pytest.mark.parametrize("n", [(2048, 8, 8), (8, 8, 1152)])
+def test_longest_lines(n):
+    """The longest transform lengths the kernels accept (L = 4096 FP32, 2304 FP64)."""
+    say(f"[longest] n={n}")
+    h = (0.01, 0.02, 0.03)
+    S = sources.random_field(n, seed=5).numpy()
+    ref = oracle.solve_fft(S, h)
+    got64 = gpu_solve(n, h, S, torch.float64) if max(n) <= 1152 else None
+    got32 = gpu_solve(n, h, S, torch.float32)
+    if got64 is not None:
+        r64 = norms.report(got64, ref)
+        say(f"  fp64 {r64}")
+        assert r64["rel_l2"] <= FP64_TOL and r64["rel_max"] <= FP64_TOL
+    r32 = norms.report(got32, ref)
+    say(f"  fp32 {r32}")
+    assert r32["rel_l2"] <= FP32_TOL
+
+
+# ------------------------------------------------------------- large sizes --
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_config5_n512_sampled_direct_sum(dtype):
+    """Full-size 512^3 (1024^3 padded) solve checked at sampled targets by the direct sum."""
+    from paper_1106_0557_amd import Plan
+
+    say(f"[config5] n=512 {dtype}")
+    n, h, S = sources.config5(device="cuda")
+    S = S.cpu()
+    rng = np.random.default_rng(55)
+    targets = np.unique(rng.integers(0, n**3, size=24))
+    targets = np.concatenate([targets, [0, n**3 - 1, (n // 2) * (n * n + n + 1)]])
+    want = oracle.direct(S.numpy(), h, targets)
+    plan = Plan(n, n, n, h=h, dtype=dtype)
+    phi = plan.solve(S.to("cuda", dtype))
+    torch.cuda.synchronize()
+    got = phi.reshape(-1)[torch.from_numpy(targets).cuda()].double().cpu().numpy()
+    plan.close()
+    del phi
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say(f"  sampled rel max err {err:.3e}")
+    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
