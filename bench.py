@@ -28,8 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "solves/s + effective HBM GB/s at 256^3 (FP32 served vs FP64 plain); p50/p99"
-KERNEL_SOURCES = ("paper_1106_0557_amd/csrc/pspfft_kernels.hip", "paper_1106_0557_amd/csrc/pspfft_runtime.cpp",
-                  "paper_1106_0557_amd/csrc/internal.h")
+CSRC = "paper_1106_0557_amd/csrc"
 
 
 def algorithmic_bytes(n: int, real: int) -> int:
@@ -50,10 +49,14 @@ def percentile(xs, q):
 
 
 def source_hash() -> str:
+    """Hash of every kernel and runtime source, to tie counter data to a build."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+    d = os.path.join(ROOT, CSRC)
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -175,6 +178,21 @@ def main():
     acc32 = {"rel_l2_vs_gpu_fp64": float(d.norm() / phi64.norm()),
              "rel_max_vs_gpu_fp64": float(d.abs().max() / phi64.abs().max())}
 
+    # ------------------------------------------ device copy ceiling (context)
+    cbytes = 1 << 30
+    ca = torch.empty(cbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * cbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
+
     # ---------------------------------------------------- FP64 plain (timed)
     out64 = torch.empty_like(S64_dev)
     for _ in range(20):
@@ -253,6 +271,7 @@ def main():
                                f"in grouped launches",
                    "n": n, "padded": 2 * n, "batch_per_step": B, "parallelism": "single-gpu"},
         "effective_GBps": round(eff32, 1),
+        "copy_ceiling_GBps": round(copy_gbs, 1),
         "roofline_frac_effective": round(eff32 / HBM_PEAK_GBS, 4),
         "algorithmic_bytes_per_solve": bytes32,
         "step_ms_p50": round(percentile(step_ms, 50), 5),

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-parameter",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-DEVICE_SOURCES = ["pspfft_kernels.hip"]
+DEVICE_SOURCES = ["green.hip"] + [f"pass_{p}_e{e}.hip" for p in ("f32", "f64") for e in (16, 20, 24, 36)]
 HOST_SOURCES = ["pspfft_runtime.cpp"]
 
 
@@ -29,7 +29,7 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = True, jobs: int = 4) -> str:
+def build(verbose: bool = True, jobs: int = 8) -> str:
     out_dir = tempfile.mkdtemp(prefix="pspfft_build_")
     objs = []
     procs = []

@@ -24,21 +24,27 @@ namespace pspfft {
 constexpr int kMaxStages = 10;
 constexpr int kMaxProblems = 32;  // problems per grouped launch
 
-// One line length L = 2n along one axis, split into stages of radix R[s].
+// One transform line along one axis, split into stages of radix R[s].
+// y and z lines have length L = 2n (the doubled mesh).  x lines use the packed
+// real-to-complex form: the 2n real values of a zero-padded row become n
+// complex values, so L = n there, plus a split step with exp(-i pi k / n).
 // A line is handled by NB = L / E threads, each owning the E positions
-// t + NB*m (m < E) before the first and after the last stage.
+// t + NB*m (m < E) before the first and after the last stage; the upper half of
+// the input (m >= E/2) is the zero padding and the upper half of the output is
+// never needed, so both are known at compile time.
 struct AxisPlan {
     int n;        // mesh cells along the axis
-    int L;        // transform length, 2n
+    int L;        // transform length (2n for y and z, n for x)
     int E;        // elements per thread (radix family: 16, 20, 24 or 36)
     int NB;       // threads per line
     int nst;      // number of stages
-    int pad_;
+    int ntw;      // entries in the twiddle table
     int R[kMaxStages];          // radix of stage s
     int Ns[kMaxStages];         // product of the radices before stage s
     uint32_t magic[kMaxStages]; // floor(2^32 / Ns) + 1, for b / Ns
     int twoff[kMaxStages];      // offset of stage s in the twiddle table
     const void *tw;             // twiddles exp(-2 pi i r k / (Ns R)), k < Ns, 1 <= r < R
+    const void *post;           // x only: exp(-i pi k / n), k < n
 };
 
 struct DevPlan {
@@ -55,25 +61,85 @@ struct ProbArg {
     void *Phi;        // potential (x inverse pass)
     void *W;          // workspace main part
     void *Wn;         // workspace Nyquist column
-    int wg_begin;     // first workgroup of this problem in the launch
-    int wg_main;      // workgroups for the main lines; the rest handle Nyquist lines
+};
+
+// A run of `group` consecutive problems p[first .. first+group) with the same
+// plan.  Its workgroups are numbered tile-major (tile, member), so the members
+// that read the same spectrum slice are neighbours in the launch.
+struct Segment {
+    int wg_begin;     // first workgroup of the segment
+    int first;        // index of its first problem in LaunchArgs::p
+    int group;        // problems in the segment
+    int wg_main;      // tiles of main lines per problem; the rest are Nyquist lines
 };
 
 struct LaunchArgs {
     int count;        // problems in this launch
-    int pad_;
+    int nseg;         // segments
+    int nwg;          // workgroups doing work (the grid may be padded to a multiple of 8)
+    int xcd_remap;    // renumber workgroups so each XCD gets a contiguous range
+    Segment seg[kMaxProblems];
     ProbArg p[kMaxProblems];
 };
 
 enum PassMode { X_FWD = 0, Y_FWD = 1, Z_CONV = 2, Y_INV = 3, X_INV = 4 };
 
+// LDS layout of a workgroup (complex elements), identical on host and device.
+// Column passes keep element (line c, position P) at P*(tile+1) + c; row passes
+// at c*S + P + P/16, with S chosen so that the NB-lane chunks of consecutive
+// rows fall on different banks.
+__host__ __device__ inline int row_stride(int L, int NB, int csz) {
+    int S = L + (L >> 4);
+    const int chunk = NB * csz;
+    if (chunk < 256) {
+        const int want = chunk % 256;
+        while ((S * csz) % 256 != want) ++S;
+    }
+    return S;
+}
+__host__ __device__ inline int data_elems(bool row, int L, int NB, int block, int csz) {
+    const int tile = block / NB;
+    return row ? tile * row_stride(L, NB, csz) : L * (tile + 1);
+}
+
 inline int pass_axis(int mode) { return mode == X_FWD || mode == X_INV ? 0 : (mode == Z_CONV ? 2 : 1); }
 
-// Launchers (defined in pspfft_kernels.hip).  `block` threads per workgroup,
-// `lds_bytes` dynamic shared memory.
-hipError_t launch_pass(int mode, int prec, int E, const LaunchArgs &args, int grid, int block,
-                       size_t lds_bytes, hipStream_t stream);
-int max_block(int prec, int E);
+// Largest workgroup per (precision, radix family), chosen so that the E
+// registers per thread fit without spilling.
+__host__ __device__ constexpr int max_block_for(int prec, int E) {
+    return prec == 0 ? (E == 16 ? 1024 : (E <= 24 ? 512 : 256)) : (E == 16 ? 512 : 256);
+}
+
+// Launchers: one per (precision, family), defined in pass_<prec>_e<E>.hip.
+// K is the radix of the last stage of the pass axis (1 for a single stage).
+#define PSPFFT_DECLARE_FAMILY(NAME)                                                                 \
+    hipError_t NAME(int mode, int K, const LaunchArgs &args, int grid, int block, size_t lds,       \
+                    hipStream_t stream);
+PSPFFT_DECLARE_FAMILY(launch_f32_e16)
+PSPFFT_DECLARE_FAMILY(launch_f32_e20)
+PSPFFT_DECLARE_FAMILY(launch_f32_e24)
+PSPFFT_DECLARE_FAMILY(launch_f32_e36)
+PSPFFT_DECLARE_FAMILY(launch_f64_e16)
+PSPFFT_DECLARE_FAMILY(launch_f64_e20)
+PSPFFT_DECLARE_FAMILY(launch_f64_e24)
+PSPFFT_DECLARE_FAMILY(launch_f64_e36)
+#undef PSPFFT_DECLARE_FAMILY
+
+inline hipError_t launch_pass(int mode, int prec, int E, int K, const LaunchArgs &args, int grid, int block,
+                              size_t lds, hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
+    switch (prec * 100 + E) {
+        case 16: return launch_f32_e16(mode, K, args, grid, block, lds, stream);
+        case 20: return launch_f32_e20(mode, K, args, grid, block, lds, stream);
+        case 24: return launch_f32_e24(mode, K, args, grid, block, lds, stream);
+        case 36: return launch_f32_e36(mode, K, args, grid, block, lds, stream);
+        case 116: return launch_f64_e16(mode, K, args, grid, block, lds, stream);
+        case 120: return launch_f64_e20(mode, K, args, grid, block, lds, stream);
+        case 124: return launch_f64_e24(mode, K, args, grid, block, lds, stream);
+        case 136: return launch_f64_e36(mode, K, args, grid, block, lds, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 // Green's-function spectrum in FP64: fills the octant (nz+1)(ny+1)(nx+1) of G
 // into `a`, applies the even-extension cosine transform along each axis (using

@@ -1,0 +1,427 @@
+// pass_kernels.h -- the five streaming passes of one mesh-doubling solve
+// (Budiardja & Cardall, arXiv:1106.0557, Sec. 2.1 and 2.2.2) as gfx950 kernels.
+//
+//   X_FWD  : rows of S, zero-padded to 2nx, transformed along x (packed real form)
+//   Y_FWD  : columns along y; the input half y >= ny is zero and never read
+//   Z_CONV : columns along z: forward transform (input half zero), multiply by the
+//            Green's-function spectrum, inverse transform, keep z < nz (Sec. 2.1,
+//            convolution theorem; Sec. 2.2.2, the multiply happens in z pillars)
+//   Y_INV  : inverse along y, keep y < ny
+//   X_INV  : inverse along x with the Hermitian extension, keep x < nx -> Phi
+// The normalisation 1/((2nx)(2ny)(2nz)) is folded into the spectrum.
+//
+// Line engine.  A line of length L is owned by NB = L/E threads of a workgroup;
+// thread t holds positions t + NB*m (m < E) in registers.  Stages (Stockham,
+// decimation in time) have radix E first, then M (the power-of-two part of E) in
+// the middle, then K last; every radix divides E, so each thread applies E/R
+// butterflies per stage.  Stage 0 reads the registers the caller loaded from
+// global memory and scatters to LDS; middle stages go LDS -> LDS; the last stage
+// gathers from LDS and leaves its outputs in the thread's own positions, in
+// registers.  E and K are template parameters, so no line data is carried in
+// registers across a runtime branch or loop back-edge.  The zero half of an input
+// and the discarded half of an output are registers m >= E/2, known at compile
+// time, so their butterfly arithmetic is removed by the compiler.
+#pragma once
+
+#include "fft_core.h"
+#include "internal.h"
+
+namespace pspfft {
+
+template <typename T, int E, int DIR, bool ROW>
+struct LineFFT {
+    static constexpr int M = E & -E;  // radix of the middle stages
+
+    // LDS layout: column passes keep (line c, position P) at P*ldsw + c with
+    // ldsw = tile + 1; row passes at c*ldsw + P + P/16 with ldsw = row_stride().
+    static __device__ __forceinline__ void gather(cx<T> *v, const cx<T> *lds, int ldsw, int c, int t, int NB) {
+        if constexpr (ROW) {
+            const cx<T> *row = lds + c * ldsw;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int P = t + NB * m;
+                v[m] = row[P + (P >> 4)];
+            }
+        } else {
+            const cx<T> *col = lds + t * ldsw + c;
+            const int step = NB * ldsw;
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = col[m * step];
+        }
+    }
+
+    // E/R radix-R butterflies on the thread's registers.  Stage parameters:
+    // Ns = product of the earlier radices, mg its division magic, tw the stage's
+    // twiddle table.  TW: multiply by twiddles (every stage but the first).
+    // TO_LDS: scatter the outputs to their Stockham positions in LDS; otherwise
+    // (last stage) they land in the thread's own positions, in registers.
+    template <int R, bool TW, bool TO_LDS>
+    static __device__ __forceinline__ void stage(cx<T> *v, int Ns, uint32_t mg, const cx<T> *tw, cx<T> *lds,
+                                                 int ldsw, int c, int t, int NB) {
+        constexpr int NBF = E / R;
+        sfor<0, NBF>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const int b = t + NB * i;
+            int q = b, k = 0;
+            if constexpr (TW) {
+                q = static_cast<int>(__umulhi(static_cast<uint32_t>(b), mg));
+                k = b - q * Ns;
+            }
+            cx<T> x[R];
+            sfor<0, R>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                x[r] = v[i + r * NBF];
+            });
+            if constexpr (TW) {
+                const cx<T> *twk = tw + k * (R - 1);
+                sfor<1, R>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    const cx<T> w = twk[r - 1];
+                    if constexpr (DIR > 0) x[r] = cmulc(x[r], w);
+                    else x[r] = cmul(x[r], w);
+                });
+            }
+            dft<R, DIR>(x);
+            if constexpr (TO_LDS) {
+                const int base = q * Ns * R + k;  // output r goes to position base + r*Ns
+                if constexpr (ROW) {
+                    cx<T> *row = lds + c * ldsw;
+                    sfor<0, R>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        const int P = base + r * Ns;
+                        row[P + (P >> 4)] = x[r];
+                    });
+                } else {
+                    cx<T> *col = lds + base * ldsw + c;
+                    const int step = Ns * ldsw;
+                    sfor<0, R>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        col[r * step] = x[r];
+                    });
+                }
+            } else {
+                sfor<0, R>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    v[i + r * NBF] = x[r];
+                });
+            }
+        });
+    }
+
+    // Transform the line whose positions t + NB*m the thread holds in v[m].
+    // K = radix of the last stage (1: the whole line is one radix-E stage).
+    // twl: stage twiddle tables in LDS, published by the first barrier.
+    template <int K>
+    static __device__ __forceinline__ void run(cx<T> *v, const AxisPlan &ax, cx<T> *lds, int ldsw,
+                                               const cx<T> *twl, int c, int t) {
+        const int NB = ax.NB;
+        if constexpr (K == 1) {
+            stage<E, false, false>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
+        } else {
+            __syncthreads();  // earlier readers of LDS are done
+            stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
+            const int last = ax.nst - 1;
+            for (int s = 1; s < last; ++s) {
+                __syncthreads();
+                gather(v, lds, ldsw, c, t, NB);
+                __syncthreads();
+                stage<M, true, true>(v, ax.Ns[s], ax.magic[s], twl + ax.twoff[s], lds, ldsw, c, t, NB);
+            }
+            __syncthreads();
+            gather(v, lds, ldsw, c, t, NB);
+            stage<K, true, false>(v, ax.Ns[last], ax.magic[last], twl + ax.twoff[last], lds, ldsw, c, t, NB);
+        }
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void copy_to_lds(cx<T> *dst, const void *src, int count) {
+    const cx<T> *s = static_cast<const cx<T> *>(src);
+    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = s[i];
+}
+
+template <typename T, int E, int K, int MODE>
+__global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pass_kernel(const LaunchArgs args) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
+    constexpr bool ROW = (MODE == X_FWD || MODE == X_INV);
+    constexpr int H = E / 2;  // registers m < H hold the first half of the line
+    using FFT_F = LineFFT<T, E, -1, ROW>;
+    using FFT_I = LineFFT<T, E, +1, ROW>;
+
+    // XCD-aware order: hardware hands consecutive workgroups to the 8 XCDs in
+    // turn; renumber so that each XCD works through a contiguous range of the
+    // launch (neighbouring tiles, and the same tile of batched problems that
+    // share a spectrum, then meet in one L2).
+    const int nwg = static_cast<int>(gridDim.x);
+    const int bx = static_cast<int>(blockIdx.x);
+    int bid = bx;
+    if (args.xcd_remap == 1) {         // each XCD takes one contiguous eighth of the launch
+        const int per = nwg >> 3;      // the grid is a multiple of 8 when remapping
+        bid = (bx & 7) * per + (bx >> 3);
+    } else if (args.xcd_remap == 2) {  // within each block of 64, each XCD takes 8 in a row
+        bid = (bx & ~63) + ((bx & 7) << 3) + ((bx >> 3) & 7);
+    }
+    if (bid >= args.nwg) return;  // padding of the grid to a multiple of 8
+    int sgi = 0;
+    while (sgi + 1 < args.nseg && bid >= args.seg[sgi + 1].wg_begin) ++sgi;
+    const Segment &sg = args.seg[sgi];
+    int local = bid - sg.wg_begin;
+    const int member = local % sg.group;  // segments are tiled tile-major
+    local /= sg.group;
+    const ProbArg &pa = args.p[sg.first + member];
+    const DevPlan &pl = *pa.plan;
+    constexpr int axis = ROW ? 0 : (MODE == Z_CONV ? 2 : 1);
+    const AxisPlan &ax = pl.ax[axis];
+    const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
+    const int NB = ax.NB;
+    const int L = ax.L;
+    const int block = static_cast<int>(blockDim.x);
+    const int tile = block / NB;  // lines per workgroup (power of two)
+    const int tid = threadIdx.x;
+    int c, t;
+    if constexpr (ROW) {  // rows are contiguous in memory: consecutive lanes walk along a row
+        t = tid & (NB - 1);
+        c = tid >> __builtin_ctz(NB);
+    } else {              // columns: consecutive lanes take adjacent lines (adjacent kx)
+        c = tid & (tile - 1);
+        t = tid >> __builtin_ctz(tile);
+    }
+    const int ldsw = ROW ? row_stride(L, NB, static_cast<int>(sizeof(cx<T>))) : tile + 1;
+    cx<T> *twl = lds + data_elems(ROW, L, NB, block, static_cast<int>(sizeof(cx<T>)));
+    copy_to_lds<T>(twl, ax.tw, ax.ntw);
+
+    const bool nyq = local >= sg.wg_main;
+    if (nyq) local -= sg.wg_main;
+    const int g = local * tile + c;  // line index within its set
+
+    cx<T> v[E];
+    cx<T> *W = static_cast<cx<T> *>(pa.W);
+    cx<T> *Wn = static_cast<cx<T> *>(pa.Wn);
+
+    if constexpr (ROW) {
+        // Rows (y, z), y < ny, z < nz; row r = z*ny + y.  Packed real transform of
+        // length n: u[j] = s[2j] + i s[2j+1], zero for j >= n/2 (the padding).
+        cx<T> *post = twl + ax.ntw;  // exp(-i pi k / n), k < n
+        copy_to_lds<T>(post, ax.post, L);
+        const int nrows = ny * nz;
+        const bool active = g < nrows;
+        const int z = active ? g / ny : 0;
+        const int y = g - z * ny;
+        cx<T> *wrow = W + (static_cast<size_t>(z) * 2 * ny + y) * nx;
+        cx<T> *wnyq = Wn + static_cast<size_t>(z) * 2 * ny + y;
+        if constexpr (MODE == X_FWD) {
+            const cx<T> *srow =
+                reinterpret_cast<const cx<T> *>(static_cast<const T *>(pa.S) + static_cast<size_t>(g) * nx) + t;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (m < H && active) v[m] = srow[NB * m];
+                else v[m] = cx<T>{T(0), T(0)};
+            }
+            FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
+            // split: X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k])
+            __syncthreads();
+            {
+                cx<T> *row = lds + c * ldsw;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int P = t + NB * m;
+                    row[P + (P >> 4)] = v[m];
+                }
+            }
+            __syncthreads();
+            if (active) {
+                const cx<T> *row = lds + c * ldsw;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int k = t + NB * m;
+                    const int kp = k == 0 ? 0 : L - k;
+                    const cx<T> u = v[m];
+                    const cx<T> w = row[kp + (kp >> 4)];
+                    const cx<T> a = {static_cast<T>(0.5) * (u.x + w.x), static_cast<T>(0.5) * (u.y - w.y)};
+                    const cx<T> b = {static_cast<T>(0.5) * (u.x - w.x), static_cast<T>(0.5) * (u.y + w.y)};
+                    const cx<T> eb = cmul(post[k], b);
+                    wrow[k] = cx<T>{a.x + eb.y, a.y - eb.x};  // a - i e b
+                    if (k == 0) *wnyq = cx<T>{u.x - u.y, T(0)};
+                }
+            }
+        } else {
+            // U[k] = (X[k] + X*[n-k]) + i exp(+i pi k/n) (X[k] - X*[n-k]), k < n.
+            // Each thread loads its own X[k]; the partners come through LDS.
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (active) v[m] = wrow[t + NB * m];
+                else v[m] = cx<T>{T(0), T(0)};
+            }
+            cx<T> xn = {T(0), T(0)};
+            if (active) xn = *wnyq;
+            {
+                cx<T> *row = lds + c * ldsw;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int P = t + NB * m;
+                    row[P + (P >> 4)] = v[m];
+                }
+            }
+            __syncthreads();  // row values, post table and twiddles visible
+            {
+                const cx<T> *row = lds + c * ldsw;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int k = t + NB * m;
+                    const int kp = L - k;
+                    const cx<T> a = v[m];
+                    const cx<T> b = k == 0 ? xn : row[kp + (kp >> 4)];
+                    const cx<T> sm = {a.x + b.x, a.y - b.y};
+                    const cx<T> df = {a.x - b.x, a.y + b.y};
+                    const cx<T> ed = cmulc(df, post[k]);
+                    v[m] = cx<T>{sm.x - ed.y, sm.y + ed.x};
+                }
+            }
+            FFT_I::template run<K>(v, ax, lds, ldsw, twl, c, t);
+            if (active) {
+                cx<T> *prow =
+                    reinterpret_cast<cx<T> *>(static_cast<T *>(pa.Phi) + static_cast<size_t>(g) * nx) + t;
+#pragma unroll
+                for (int m = 0; m < H; ++m) prow[NB * m] = v[m];
+            }
+        }
+    } else {
+        // Column passes: line g starts at `base`, elements `es` apart.
+        cx<T> *base;
+        size_t es;
+        bool active;
+        int ky = 0, kx = 0;
+        if constexpr (MODE == Z_CONV) {
+            // Rows of the plane are visited in the order 0, 1, 2ny-1, 2, 2ny-2, ...,
+            // ny, so that ky and its mirror 2ny - ky (same spectrum values) are
+            // handled by neighbouring workgroups.
+            if (!nyq) {
+                active = g < 2 * ny * nx;
+                const int vrow = active ? g / nx : 0;
+                kx = g - vrow * nx;
+                ky = vrow == 0 ? 0 : (vrow == 2 * ny - 1 ? ny : ((vrow & 1) ? (vrow + 1) >> 1 : 2 * ny - (vrow >> 1)));
+                base = W + static_cast<size_t>(ky) * nx + kx;
+                es = static_cast<size_t>(2) * ny * nx;
+            } else {
+                active = g < 2 * ny;
+                ky = g;
+                kx = nx;
+                base = Wn + g;
+                es = static_cast<size_t>(2) * ny;
+            }
+        } else {
+            if (!nyq) {
+                active = g < nz * nx;
+                const int z = active ? g / nx : 0;
+                kx = g - z * nx;
+                base = W + static_cast<size_t>(z) * 2 * ny * nx + kx;
+                es = nx;
+            } else {
+                active = g < nz;
+                base = Wn + static_cast<size_t>(g) * 2 * ny;
+                es = 1;
+            }
+        }
+        cx<T> *lane = base + t * es;  // this thread's position t; position t + NB*m is m*step further
+        const size_t step = static_cast<size_t>(NB) * es;
+        // Forward transforms read only the stored half (m < H); inverse ones
+        // read the whole line.
+        constexpr int nload = (MODE == Y_INV) ? E : H;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            if (m < nload && active) v[m] = lane[m * step];
+            else v[m] = cx<T>{T(0), T(0)};
+        }
+        if constexpr (MODE == Y_FWD) {
+            FFT_F::template run<K>(v, ax, lds, tile + 1, twl, c, t);
+        } else if constexpr (MODE == Y_INV) {
+            FFT_I::template run<K>(v, ax, lds, tile + 1, twl, c, t);
+        } else {
+            // Spectrum values for this thread's kz positions, fetched with the line
+            // so that both memory latencies overlap.  G~ is even in ky and kz: octant
+            // index min(k, 2n - k); for position P = t + NB*m that is t + NB*m when
+            // m < H and NB*(E - m) - t otherwise.
+            const int kyo = ky <= ny ? ky : 2 * ny - ky;
+            const T *Gp = nyq ? static_cast<const T *>(pl.Gn) + kyo
+                              : static_cast<const T *>(pl.G) + static_cast<size_t>(kyo) * nx + kx;
+            const size_t gs = nyq ? static_cast<size_t>(ny + 1) : static_cast<size_t>(ny + 1) * nx;
+            const T *glo = Gp + t * gs;
+            const T *ghi = Gp - t * gs;
+            const size_t gstep = static_cast<size_t>(NB) * gs;
+            T gv[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                if (active) gv[m] = m < H ? glo[m * gstep] : ghi[(E - m) * gstep];
+                else gv[m] = T(0);
+            }
+            FFT_F::template run<K>(v, ax, lds, tile + 1, twl, c, t);
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = scale(v[m], gv[m]);
+            FFT_I::template run<K>(v, ax, lds, tile + 1, twl, c, t);
+        }
+        // Inverse transforms keep only the first half (m < H).
+        constexpr int nstore = (MODE == Y_FWD) ? E : H;
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < nstore; ++m) lane[m * step] = v[m];
+        }
+    }
+}
+
+template <typename T, int E, int K, int MODE>
+hipError_t launch_kernel(const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
+    static bool attr_set = false;
+    auto fn = pass_kernel<T, E, K, MODE>;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, stream, args);
+    return hipGetLastError();
+}
+
+template <typename T, int E, int K>
+hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
+    switch (mode) {
+        case X_FWD: return launch_kernel<T, E, K, X_FWD>(args, grid, block, lds, stream);
+        case Y_FWD: return launch_kernel<T, E, K, Y_FWD>(args, grid, block, lds, stream);
+        case Z_CONV: return launch_kernel<T, E, K, Z_CONV>(args, grid, block, lds, stream);
+        case Y_INV: return launch_kernel<T, E, K, Y_INV>(args, grid, block, lds, stream);
+        case X_INV: return launch_kernel<T, E, K, X_INV>(args, grid, block, lds, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// All last-stage radices a family can have: 1 (single stage) and the powers of
+// two up to the middle radix.
+template <typename T, int E>
+hipError_t launch_family(int mode, int K, const LaunchArgs &args, int grid, int block, size_t lds,
+                         hipStream_t stream) {
+    constexpr int M = E & -E;
+    switch (K) {
+        case 1: return launch_mode<T, E, 1>(mode, args, grid, block, lds, stream);
+        case 2: return launch_mode<T, E, 2>(mode, args, grid, block, lds, stream);
+        case 4: return launch_mode<T, E, 4>(mode, args, grid, block, lds, stream);
+        case 8:
+            if constexpr (M >= 8) return launch_mode<T, E, 8>(mode, args, grid, block, lds, stream);
+            else return hipErrorInvalidValue;
+        case 16:
+            if constexpr (M >= 16) return launch_mode<T, E, 16>(mode, args, grid, block, lds, stream);
+            else return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace pspfft
+
+// One translation unit per (precision, family) keeps compiles parallel.
+#define PSPFFT_FAMILY(T, E, NAME)                                                                   \
+    namespace pspfft {                                                                              \
+    hipError_t NAME(int mode, int K, const LaunchArgs &args, int grid, int block, size_t lds,       \
+                    hipStream_t stream) {                                                           \
+        return launch_family<T, E>(mode, K, args, grid, block, lds, stream);                        \
+    }                                                                                               \
+    }

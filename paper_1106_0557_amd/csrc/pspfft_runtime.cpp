@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -71,15 +72,33 @@ int log_level() {
         }                                         \
     } while (0)
 
+// Workgroup renumbering for the XCDs, per pass (0 none, 1 contiguous eighths,
+// 2 runs of 8 within blocks of 64).  PSPFFT_XCD_REMAP="abcde" overrides the
+// five passes in order.
+int xcd_remap_mode(int mode) {
+    static int modes[5] = {-1, -1, -1, -1, -1};
+    if (modes[0] < 0) {
+        const int dflt[5] = {1, 0, 0, 0, 1};
+        const char *e = std::getenv("PSPFFT_XCD_REMAP");
+        for (int i = 0; i < 5; ++i) {
+            int v = dflt[i];
+            if (e && std::strlen(e) == 5 && e[i] >= '0' && e[i] <= '2') v = e[i] - '0';
+            modes[i] = v;
+        }
+    }
+    return (mode >= 0 && mode < 5) ? modes[mode] : 0;
+}
+
 size_t real_size(pspfft_precision p) { return p == PSPFFT_FP32 ? 4 : 8; }
 size_t cplx_size(pspfft_precision p) { return 2 * real_size(p); }
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Radix family of a transform length L = 2n: the odd part o of L selects E, the
-// elements each thread owns; every stage radix divides E.
-int family_of(int n) {
-    if (n < 1) return 0;
-    int m = n;
+// Radix family of a transform length L: the odd part o of L selects E, the
+// elements each thread owns (every stage radix divides E); L must be a multiple
+// of E.  y and z transforms have L = 2n; the packed x transform has L = n.
+int family_of_len(int L) {
+    if (L < 1) return 0;
+    int m = L;
     while (m % 2 == 0) m /= 2;
     int E = 0;
     if (m == 1) E = 16;
@@ -87,14 +106,21 @@ int family_of(int n) {
     else if (m == 5) E = 20;
     else if (m == 9) E = 36;
     else return 0;
-    const int L = 2 * n;
     if (L < E || L % E != 0) return 0;
     return E;
 }
 
+int axis_len(int axis, int n) { return axis == 0 ? n : 2 * n; }
+
 int max_n(pspfft_precision p) { return p == PSPFFT_FP32 ? 2048 : 1152; }
 
-bool size_ok(int n, pspfft_precision p) { return n >= 1 && n <= max_n(p) && family_of(n) != 0; }
+bool size_ok(int axis, int n, pspfft_precision p) {
+    return n >= 1 && n <= max_n(p) && family_of_len(axis_len(axis, n)) != 0;
+}
+
+bool sizes_ok(int nx, int ny, int nz, pspfft_precision p) {
+    return size_ok(0, nx, p) && size_ok(1, ny, p) && size_ok(2, nz, p);
+}
 
 // cos and sin of 2 pi j / M in double precision, folded into [0, pi/4] first.
 void turn(long j, long M, double &c, double &s) {
@@ -114,15 +140,16 @@ void turn(long j, long M, double &c, double &s) {
 }
 
 // Stage plan and FP64 twiddles of one axis.
-bool build_axis(int n, AxisPlan &ax, std::vector<std::complex<double>> &tw) {
-    const int E = family_of(n);
+bool build_axis(int axis, int n, AxisPlan &ax, std::vector<std::complex<double>> &tw) {
+    const int L = axis_len(axis, n);
+    const int E = family_of_len(L);
     if (!E) return false;
     std::memset(&ax, 0, sizeof(ax));
     ax.n = n;
-    ax.L = 2 * n;
+    ax.L = L;
     ax.E = E;
-    ax.NB = ax.L / E;
-    int rem = ax.L, Ns = 1, s = 0;
+    ax.NB = L / E;
+    int rem = L, Ns = 1, s = 0;
     tw.clear();
     while (rem > 1) {
         if (s >= pspfft::kMaxStages) return false;
@@ -132,7 +159,7 @@ bool build_axis(int n, AxisPlan &ax, std::vector<std::complex<double>> &tw) {
         ax.Ns[s] = Ns;
         ax.magic[s] = Ns > 1 ? static_cast<uint32_t>((uint64_t(1) << 32) / Ns + 1) : 0u;
         if (Ns > 1) {  // verify the multiply-high division for every index used
-            for (uint32_t b = 0; b < static_cast<uint32_t>(ax.L); ++b) {
+            for (uint32_t b = 0; b < static_cast<uint32_t>(L); ++b) {
                 const uint32_t q = static_cast<uint32_t>((uint64_t(b) * ax.magic[s]) >> 32);
                 if (q != b / static_cast<uint32_t>(Ns)) return false;
             }
@@ -149,8 +176,16 @@ bool build_axis(int n, AxisPlan &ax, std::vector<std::complex<double>> &tw) {
         ++s;
     }
     ax.nst = s;
-    if (tw.empty()) tw.emplace_back(1.0, 0.0);  // keep a valid pointer for one-stage lines
-    return Ns == ax.L;
+    ax.ntw = static_cast<int>(tw.size());
+    if (axis == 0) {  // split-step factors exp(-i pi k / n) of the packed real transform
+        for (int k = 0; k < n; ++k) {
+            double c, sn;
+            turn(-static_cast<long>(k), 2L * n, c, sn);
+            tw.emplace_back(c, sn);
+        }
+    }
+    if (tw.empty()) tw.emplace_back(1.0, 0.0);
+    return Ns == L;
 }
 
 // cos(pi j / n), j < 2n, for the even-extension transform of G.
@@ -234,19 +269,33 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
     if (mode == pspfft::X_INV && !Phi) return PSPFFT_ERR_INVALID_ARGUMENT;
     for (int i = 0; i < count; ++i) {
         if (!plans[i] || !ws[i] || ws[i]->plan != plans[i]) return PSPFFT_ERR_INVALID_ARGUMENT;
-        if (mode == pspfft::X_FWD && !S[i]) return PSPFFT_ERR_INVALID_ARGUMENT;
-        if (mode == pspfft::X_INV && !Phi[i]) return PSPFFT_ERR_INVALID_ARGUMENT;
+        // the x passes move pairs of reals: S and Phi must be aligned to two reals
+        const uintptr_t al = 2 * real_size(plans[i]->prec);
+        if (mode == pspfft::X_FWD && (!S[i] || reinterpret_cast<uintptr_t>(S[i]) % al)) return PSPFFT_ERR_INVALID_ARGUMENT;
+        if (mode == pspfft::X_INV && (!Phi[i] || reinterpret_cast<uintptr_t>(Phi[i]) % al))
+            return PSPFFT_ERR_INVALID_ARGUMENT;
     }
     const int axis = pspfft::pass_axis(mode);
-    // group problems by (precision, radix family): one kernel per group
-    std::map<std::pair<int, int>, std::vector<int>> groups;
-    for (int i = 0; i < count; ++i) groups[{static_cast<int>(plans[i]->prec), plans[i]->host.ax[axis].E}].push_back(i);
+    const bool row = axis == 0;
+    // One kernel per (precision, radix family E, last-stage radix K) of the pass axis.
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    for (int i = 0; i < count; ++i) {
+        const AxisPlan &ax = plans[i]->host.ax[axis];
+        const int K = ax.nst == 1 ? 1 : ax.R[ax.nst - 1];
+        groups[{static_cast<int>(plans[i]->prec), ax.E, K}].push_back(i);
+    }
     for (auto &kv : groups) {
-        const int prec = kv.first.first, E = kv.first.second;
-        const auto &idx = kv.second;
-        const int tile_target = prec == 0 ? 16 : 8;  // 128-byte rows of complex values
-        const int bmax = pspfft::max_block(prec, E);
-        const size_t csz = prec == 0 ? 8 : 16;
+        const int prec = std::get<0>(kv.first), E = std::get<1>(kv.first), K = std::get<2>(kv.first);
+        std::vector<int> idx = kv.second;
+        // problems of one plan next to each other: they form a segment sharing spectrum reads
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            return reinterpret_cast<uintptr_t>(plans[a]) < reinterpret_cast<uintptr_t>(plans[b]);
+        });
+        // Column passes: 128-byte rows of complex values per wavefront row.
+        // Row passes: enough rows per workgroup for 256-thread groups.
+        const int tile_target = row ? (prec == 0 ? 32 : 16) : (prec == 0 ? 16 : 8);
+        const int bmax = pspfft::max_block_for(prec, E);
+        const int csz = prec == 0 ? 8 : 16;
         for (size_t c0 = 0; c0 < idx.size(); c0 += pspfft::kMaxProblems) {
             const size_t c1 = std::min(idx.size(), c0 + pspfft::kMaxProblems);
             int block = 0, nbmax = 1;
@@ -256,9 +305,19 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
                 block = std::max(block, tile_target * NB);
             }
             block = std::min(std::max(block, 64), bmax);
-            while (block > nbmax && static_cast<size_t>(block) * E * csz > 160 * 1024) block /= 2;
-            if (block < nbmax) return PSPFFT_ERR_UNSUPPORTED_SIZE;
-            const size_t lds = static_cast<size_t>(block) * E * csz;
+            auto lds_need = [&](int blk) {
+                size_t need = 0;
+                for (size_t j = c0; j < c1; ++j) {
+                    const AxisPlan &ax = plans[idx[j]]->host.ax[axis];
+                    const size_t e = static_cast<size_t>(pspfft::data_elems(row, ax.L, ax.NB, blk, csz)) + ax.ntw +
+                                     (row ? ax.L : 0);
+                    need = std::max(need, e * csz);
+                }
+                return need;
+            };
+            while (block > nbmax && lds_need(block) > 160 * 1024) block /= 2;
+            if (block < nbmax || lds_need(block) > 160 * 1024) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+            const size_t lds = lds_need(block);
             LaunchArgs args;
             std::memset(&args, 0, sizeof(args));
             args.count = static_cast<int>(c1 - c0);
@@ -266,24 +325,40 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
             for (size_t j = c0; j < c1; ++j) {
                 const int i = idx[j];
                 const pspfft_plan_t pl = plans[i];
-                const int tile = block / pl->host.ax[axis].NB;
-                long lm, ln;
-                pass_lines(mode, pl->n, lm, ln);
                 ProbArg &a = args.p[j - c0];
                 a.plan = pl->dev;
                 a.S = S ? S[i] : nullptr;
                 a.Phi = Phi ? Phi[i] : nullptr;
                 a.W = ws[i]->W;
                 a.Wn = ws[i]->Wn;
-                a.wg_begin = static_cast<int>(wg);
-                const long wm = (lm + tile - 1) / tile, wn = (ln + tile - 1) / tile;
-                a.wg_main = static_cast<int>(wm);
-                wg += wm + wn;
+                if (j > c0 && plans[idx[j - 1]] == pl) {
+                    pspfft::Segment &sg = args.seg[args.nseg - 1];
+                    sg.group += 1;
+                    continue;
+                }
+                pspfft::Segment &sg = args.seg[args.nseg++];
+                sg.first = static_cast<int>(j - c0);
+                sg.group = 1;
             }
-            if (wg > 0x7fffffffL) return PSPFFT_ERR_UNSUPPORTED_SIZE;
-            PSPFFT_LOG(3, "pass %d prec %d E %d: %d problems, %ld workgroups of %d threads, %zu B LDS", mode, prec, E,
-                       args.count, wg, block, lds);
-            if (pspfft::launch_pass(mode, prec, E, args, static_cast<int>(wg), block, lds, stream) != hipSuccess)
+            for (int k = 0; k < args.nseg; ++k) {
+                pspfft::Segment &sg = args.seg[k];
+                const pspfft_plan_t pl = plans[idx[c0 + sg.first]];
+                const int tile = block / pl->host.ax[axis].NB;
+                long lm, ln;
+                pass_lines(mode, pl->n, lm, ln);
+                const long wm = (lm + tile - 1) / tile, wn = (ln + tile - 1) / tile;
+                sg.wg_begin = static_cast<int>(wg);
+                sg.wg_main = static_cast<int>(wm);
+                wg += (wm + wn) * sg.group;
+            }
+            if (wg + 8 > 0x7fffffffL) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+            args.nwg = static_cast<int>(wg);
+            args.xcd_remap = xcd_remap_mode(mode);
+            const long align = args.xcd_remap == 1 ? 8 : (args.xcd_remap == 2 ? 64 : 1);
+            const int grid = static_cast<int>((wg + align - 1) / align * align);
+            PSPFFT_LOG(3, "pass %d prec %d E %d K %d: %d problems in %d segments, %ld workgroups of %d threads, %zu B LDS",
+                       mode, prec, E, K, args.count, args.nseg, wg, block, lds);
+            if (pspfft::launch_pass(mode, prec, E, K, args, grid, block, lds, stream) != hipSuccess)
                 return PSPFFT_ERR_DEVICE;
         }
     }
@@ -308,7 +383,7 @@ const char *pspfft_status_string(pspfft_status s) {
 
 size_t pspfft_workspace_bytes(int nx, int ny, int nz, pspfft_precision prec) {
     if (prec != PSPFFT_FP32 && prec != PSPFFT_FP64) return 0;
-    if (!size_ok(nx, prec) || !size_ok(ny, prec) || !size_ok(nz, prec)) return 0;
+    if (!sizes_ok(nx, ny, nz, prec)) return 0;
     const int n[3] = {nx, ny, nz};
     return ws_bytes(n, prec);
 }
@@ -320,7 +395,7 @@ pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspf
     for (int a = 0; a < 3; ++a)
         if (!(std::isfinite(h[a]) && h[a] > 0.0)) return PSPFFT_ERR_INVALID_ARGUMENT;
     if (nx < 1 || ny < 1 || nz < 1) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (!size_ok(nx, prec) || !size_ok(ny, prec) || !size_ok(nz, prec)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+    if (!sizes_ok(nx, ny, nz, prec)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
 
     pspfft_plan_t p = new (std::nothrow) pspfft_plan_s();
     if (!p) return PSPFFT_ERR_OUT_OF_MEMORY;
@@ -342,7 +417,7 @@ pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspf
     // stage plans and twiddle tables (FP64, rounded once to the plan precision)
     for (int a = 0; a < 3; ++a) {
         std::vector<std::complex<double>> tw;
-        if (!build_axis(p->n[a], p->host.ax[a], tw)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+        if (!build_axis(a, p->n[a], p->host.ax[a], tw)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
         const size_t tb = tw.size() * cs;
         pspfft_status st = alloc(&p->tw[a], tb);
         if (st != PSPFFT_OK) return st;
@@ -358,6 +433,7 @@ pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspf
         }
         if (hipMemcpy(p->tw[a], buf.data(), tb, hipMemcpyHostToDevice) != hipSuccess) return PSPFFT_ERR_DEVICE;
         p->host.ax[a].tw = p->tw[a];
+        p->host.ax[a].post = a == 0 ? static_cast<char *>(p->tw[a]) + p->host.ax[a].ntw * cs : nullptr;
         bytes += tb;
     }
 

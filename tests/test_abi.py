@@ -51,9 +51,17 @@ def test_status_strings(lib):
                                   (24, True), (36, True), (40, True), (48, True), (96, True), (144, True),
                                   (1152, True), (2048, True), (4, False), (6, False), (9, False), (15, False),
                                   (7, False), (27, False), (4096, False), (0, False), (-8, False)])
-def test_supported_sizes(lib, n, ok):
-    b = lib.pspfft_workspace_bytes(n, 16, 16, 0)
-    assert (b > 0) == ok
+def test_supported_sizes_y_z(lib, n, ok):
+    assert (lib.pspfft_workspace_bytes(16, n, 16, 0) > 0) == ok
+    assert (lib.pspfft_workspace_bytes(16, 16, n, 0) > 0) == ok
+
+
+@pytest.mark.parametrize("n,ok", [(16, True), (20, True), (24, True), (36, True), (32, True), (40, True),
+                                  (48, True), (72, True), (128, True), (2048, True), (8, False), (10, False),
+                                  (12, False), (18, False), (6, False), (4096, False)])
+def test_supported_sizes_x(lib, n, ok):
+    """x uses the packed real transform of length n, so its minimum sizes are twice those of y, z."""
+    assert (lib.pspfft_workspace_bytes(n, 16, 16, 0) > 0) == ok
 
 
 def test_workspace_bytes_formula(lib):
@@ -87,7 +95,7 @@ def test_plan_create_rejects_bad_arguments_before_device_work(lib):
     assert st == 1
     st, handle = _create(lib, (0, 16, 16), (1, 1, 1))
     assert st == 1
-    for n in [(15, 16, 16), (16, 7, 16), (16, 16, 4096), (4, 16, 16)]:
+    for n in [(15, 16, 16), (16, 7, 16), (16, 16, 4096), (4, 16, 16), (8, 16, 16)]:
         st, handle = _create(lib, n, (1, 1, 1))
         assert st == 2 and handle is None
     # null out-pointer

@@ -50,7 +50,7 @@ def gpu_solve(n, h, S, dtype):
 
 # ---------------------------------------------------------------- spectrum --
 
-@pytest.mark.parametrize("n,h", [((16, 16, 16), (1 / 16,) * 3), ((12, 10, 16), (0.3, 0.2, 0.5)),
+@pytest.mark.parametrize("n,h", [((16, 16, 16), (1 / 16,) * 3), ((24, 10, 16), (0.3, 0.2, 0.5)),
                                  ((24, 18, 20), (0.05, 0.07, 0.06)), ((36, 8, 40), (1.0, 1.0, 2.0))])
 def test_green_spectrum_matches_oracle(n, h):
     from paper_1106_0557_amd import Plan
@@ -154,8 +154,8 @@ def test_each_pass_matches_oracle_stage(n):
 # ------------------------------------------------------------ whole solve --
 
 SIZES = [
-    (8, 8, 8), (16, 16, 16), (32, 32, 32), (24, 24, 24), (20, 20, 20), (36, 36, 36), (48, 32, 24),
-    (40, 12, 18), (10, 12, 16), (64, 48, 40), (96, 96, 96), (72, 18, 144),
+    (16, 8, 8), (16, 16, 16), (32, 32, 32), (24, 24, 24), (20, 20, 20), (36, 36, 36), (48, 32, 24),
+    (40, 12, 18), (20, 12, 10), (64, 48, 40), (96, 96, 96), (72, 18, 144),
 ]
 
 
@@ -248,9 +248,9 @@ def test_in_place_solve():
         plan.close()
 
 
-@pytest.mark.parametrize("n", [(2048, 8, 8), (8, 8, 1152)])
+@pytest.mark.parametrize("n", [(2048, 8, 8), (16, 8, 1152)])
 def test_longest_lines(n):
-    """The longest transform lengths the kernels accept (L = 4096 FP32, 2304 FP64)."""
+    """The longest transform lengths the kernels accept (x: L = 2048 FP32; z: L = 2304 FP64)."""
     say(f"[longest] n={n}")
     h = (0.01, 0.02, 0.03)
     S = sources.random_field(n, seed=5).numpy()
