@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per served trace")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -218,8 +219,7 @@ def main():
         try:
             from paper_1106_0557_amd import serve as serve_mod
 
-            serve = serve_mod.bench_served(n=n, dtype=torch.float32, plan=plan32, source=S32_dev,
-                                           duration_s=3.0, log=log)
+            serve = serve_mod.bench_served(n=n, dtype=torch.float32, log=log, count=args.serve_requests)
         except ImportError:
             serve = None
 

@@ -1,0 +1,391 @@
+"""Continuous-batching serving loop for isolated Poisson solves.
+
+Requests of different mesh sizes arrive over time.  Plans (twiddles and the
+Green's-function spectrum, computed once per size as in Sec. 2.2.2 of the paper)
+stay resident in device memory and are shared by every request of that size;
+workspaces are pooled.  A request is admitted when its device footprint
+(workspace + output) fits the memory budget and an in-flight slot is free.
+
+Scheduling is at pass granularity.  Each scheduler step issues, for every
+in-flight request, the next of its five passes; requests at the same pass are
+grouped into one batched launch (``pspfft_pass_batched``), and the five pass
+groups of a step go to five streams so that different requests' work overlaps
+on the device.  A request admitted while others are in flight starts its first
+pass in the next step, so a solve never waits for a whole batch to finish.
+Steps are ordered by events: every stream of step k+1 waits for all of step k.
+Results do not depend on the mix: each problem is tiled the same way whatever
+shares its launch.
+
+The executor interface (plans and byte counts, workspace pool, output
+allocation, ``begin_step``/``run_pass``/``end_step`` and ``is_done``/``wait`` on
+the step tokens) lets tests drive the same scheduler without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass
+from typing import Any, Callable, Dict, List, Optional, Sequence, Tuple
+
+NUM_PASSES = 5
+
+
+@dataclass
+class Request:
+    index: int
+    n: Tuple[int, int, int]      # (nx, ny, nz)
+    h: Tuple[float, float, float]
+    S: Any                       # source, resident on the device
+    arrival: float = 0.0         # seconds, on the scheduler's clock
+    phi: Any = None              # output, allocated at admission
+    next_pass: int = -1          # -1 waiting, 0..4 next pass to issue, 5 all issued
+    done: bool = False
+    rejected: bool = False
+    error: Optional[str] = None
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    _ws: Any = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+class GpuExecutor:
+    """Executor over the HIP library: plan cache, workspace pool, five streams."""
+
+    def __init__(self, dtype=None, device: int = 0):
+        import torch
+
+        import paper_1106_0557_amd as ps
+
+        self.torch = torch
+        self.ps = ps
+        self.dtype = dtype or torch.float32
+        self.device = device
+        self.plans: Dict[Any, Any] = {}
+        self.pool: Dict[Any, List[Any]] = collections.defaultdict(list)
+        # default priority streams only
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(NUM_PASSES)]
+        self._last_step_event = None
+
+    # ------------------------------------------------------------- plans
+    def key(self, req: Request):
+        return (req.n, req.h, self.dtype)
+
+    def plan(self, req: Request):
+        k = self.key(req)
+        p = self.plans.get(k)
+        if p is None:
+            nx, ny, nz = req.n
+            p = self.ps.Plan(nx, ny, nz, h=req.h, dtype=self.dtype)
+            self.plans[k] = p
+        return p
+
+    def workspace_bytes(self, req: Request) -> int:
+        nx, ny, nz = req.n
+        return self.ps.workspace_bytes(nx, ny, nz, self.dtype)
+
+    def output_bytes(self, req: Request) -> int:
+        nx, ny, nz = req.n
+        return nx * ny * nz * (4 if self.dtype == self.torch.float32 else 8)
+
+    def resident_bytes(self) -> int:
+        return sum(p.resident_bytes for p in self.plans.values())
+
+    # ------------------------------------------------ workspaces, outputs
+    def acquire(self, req: Request):
+        k = self.key(req)
+        if self.pool[k]:
+            ws = self.pool[k].pop()
+        else:
+            ws = self.plan(req).workspace()
+        return ws
+
+    def release(self, req: Request, ws) -> None:
+        self.pool[self.key(req)].append(ws)
+
+    def trim_pool(self) -> int:
+        """Free every pooled (idle) workspace; returns bytes released."""
+        freed = 0
+        for k, lst in self.pool.items():
+            for ws in lst:
+                freed += ws.plan.workspace_bytes
+                ws.close()
+            lst.clear()
+        return freed
+
+    def pooled_bytes(self) -> int:
+        return sum(ws.plan.workspace_bytes for lst in self.pool.values() for ws in lst)
+
+    def has_pooled(self, req: Request) -> bool:
+        return bool(self.pool[self.key(req)])
+
+    def alloc_output(self, req: Request):
+        return self.torch.empty(req.S.shape, dtype=self.dtype, device=req.S.device)
+
+    # ------------------------------------------------------------ launches
+    def begin_step(self) -> None:
+        if self._last_step_event is not None:
+            for s in self.streams:
+                s.wait_event(self._last_step_event)
+
+    def run_pass(self, p: int, reqs: Sequence[Request]) -> None:
+        ws = [r._ws for r in reqs]
+        self.ps.pass_batched(p, ws, S=[r.S for r in reqs], Phi=[r.phi for r in reqs], stream=self.streams[p])
+
+    def end_step(self):
+        torch = self.torch
+        cur = self.streams[0]
+        for s in self.streams[1:]:
+            ev = torch.cuda.Event()
+            ev.record(s)
+            cur.wait_event(ev)
+        ev = torch.cuda.Event()
+        ev.record(cur)
+        self._last_step_event = ev
+        return ev
+
+    @staticmethod
+    def is_done(token) -> bool:
+        return token.query()
+
+    @staticmethod
+    def wait(token) -> None:
+        token.synchronize()
+
+    def synchronize(self) -> None:
+        self.torch.cuda.synchronize(self.device)
+
+
+class Server:
+    """Admission by memory footprint + pass-level continuous batching.
+
+    ``budget_bytes`` bounds the device memory of in-flight requests (workspace
+    and output) plus idle pooled workspaces; resident plans are not counted (they
+    are shared and long-lived).  ``max_inflight`` bounds the requests on the
+    device, ``max_steps_ahead`` the scheduler steps enqueued but not finished.
+    """
+
+    def __init__(self, executor, budget_bytes: int, max_inflight: int = 64, max_steps_ahead: int = 2,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_inflight = max_inflight
+        self.max_steps_ahead = max_steps_ahead
+        self.clock = clock
+        self.waiting: collections.deque = collections.deque()
+        self.inflight: List[Request] = []
+        self.finished: List[Request] = []
+        self.used = executor.pooled_bytes()  # idle workspaces already held by the executor
+        self.steps: collections.deque = collections.deque()  # (token, requests completing in it)
+        self.t0 = clock()
+        self.launches = 0
+        self.max_batch = 0
+        self.max_used = 0
+
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    # ------------------------------------------------------------ requests
+    def footprint(self, req: Request) -> int:
+        return self.ex.workspace_bytes(req) + self.ex.output_bytes(req)
+
+    def submit(self, req: Request) -> None:
+        if self.footprint(req) > self.budget:
+            req.rejected = True
+            req.done = True
+            req.error = "footprint exceeds the memory budget"
+            req.t_done = self.now()
+            self.finished.append(req)
+            return
+        self.waiting.append(req)
+
+    def _admit(self) -> None:
+        while self.waiting and len(self.inflight) < self.max_inflight:
+            req = self.waiting[0]
+            reuse = self.ex.has_pooled(req)
+            need = self.ex.output_bytes(req) + (0 if reuse else self.ex.workspace_bytes(req))
+            if self.used + need > self.budget:
+                # idle pooled workspaces of other sizes give way to a waiting request
+                pooled = self.ex.pooled_bytes()
+                if pooled and not reuse and self.used - pooled + need <= self.budget:
+                    self.used -= self.ex.trim_pool()
+                else:
+                    break
+            self.waiting.popleft()
+            req._ws = self.ex.acquire(req)
+            req.phi = self.ex.alloc_output(req)
+            self.used += need
+            self.max_used = max(self.max_used, self.used)
+            req.next_pass = 0
+            req.t_admit = self.now()
+            self.inflight.append(req)
+
+    # -------------------------------------------------------------- stepping
+    def _retire(self, block: bool = False) -> None:
+        while self.steps:
+            token, reqs = self.steps[0]
+            if not self.ex.is_done(token):
+                if not block:
+                    return
+                self.ex.wait(token)
+            self.steps.popleft()
+            t = self.now()
+            for r in reqs:
+                r.done = True
+                r.t_done = t
+                self.ex.release(r, r._ws)  # back to the pool, still counted in `used`
+                r._ws = None
+                self.used -= self.ex.output_bytes(r)  # the output now belongs to the caller
+                self.finished.append(r)
+
+    def step(self) -> bool:
+        """One scheduler iteration; returns False when there is nothing to do."""
+        self._retire(block=False)
+        while len(self.steps) >= self.max_steps_ahead:
+            self._retire(block=True)
+        self._admit()
+        if not self.inflight:
+            return bool(self.waiting) or bool(self.steps)
+        groups: Dict[int, List[Request]] = collections.defaultdict(list)
+        for r in self.inflight:
+            groups[r.next_pass].append(r)
+        self.ex.begin_step()
+        for p in sorted(groups):
+            self.ex.run_pass(p, groups[p])
+            self.launches += 1
+            self.max_batch = max(self.max_batch, len(groups[p]))
+        token = self.ex.end_step()
+        completing = []
+        still = []
+        for r in self.inflight:
+            r.next_pass += 1
+            (completing if r.next_pass == NUM_PASSES else still).append(r)
+        self.inflight = still
+        self.steps.append((token, completing))
+        return True
+
+    def drain(self) -> None:
+        while self.inflight or self.waiting:
+            self.step()
+        self._retire(block=True)
+
+    # ---------------------------------------------------------- trace replay
+    def run_trace(self, requests: Sequence[Request], realtime: bool = True) -> List[Request]:
+        """Replay arrivals (``Request.arrival`` seconds after start) and serve them."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        self.t0 = self.clock()
+        while pending or self.inflight or self.waiting or self.steps:
+            now = self.now()
+            while pending and (pending[0].arrival <= now or not realtime):
+                self.submit(pending.popleft())
+            if self.inflight or self.waiting:
+                self.step()
+            else:
+                self._retire(block=False)
+                if not self.steps and pending and realtime:
+                    time.sleep(min(1e-4, max(0.0, pending[0].arrival - self.now())))
+        return self.finished
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    f = math.floor(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def summarize(finished: Sequence[Request], wall: float) -> dict:
+    ok = [r for r in finished if not r.rejected]
+    lat = [r.latency * 1e3 for r in ok]
+    return {
+        "requests": len(finished),
+        "served": len(ok),
+        "rejected": len(finished) - len(ok),
+        "solves_per_s": len(ok) / wall if wall > 0 else float("nan"),
+        "latency_ms_p50": percentile(lat, 50),
+        "latency_ms_p99": percentile(lat, 99),
+        "latency_ms_max": max(lat) if lat else float("nan"),
+        "wall_s": wall,
+    }
+
+
+def source_pool(sizes, per_size: int, seed: int, dtype, device="cuda"):
+    """Gaussian-blob sources per mesh size, generated once and kept on the device."""
+    import numpy as np
+
+    from . import sources
+
+    rng = np.random.default_rng(seed)
+    pool = {}
+    for n in sizes:
+        pool[n] = [sources.blob_field(n, sources.draw_blobs(rng, 8), device=device).to(dtype)
+                   for _ in range(per_size)]
+    return pool
+
+
+def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, count: int = 2000,
+                 budget_frac: float = 0.8, max_inflight: int = 32):
+    """Served-path measurement: closed-loop saturation, then a Poisson trace at
+    0.7 x saturation; reports solves/s and p50/p99 latency for the n^3 stream
+    and for the mixed-size stream of ``sizes``."""
+    import torch
+
+    from . import sources
+
+    dtype = dtype or torch.float32
+    free, total = torch.cuda.mem_get_info()
+    budget = int(budget_frac * free)
+    results = {}
+    streams = {"single": ((n,), (1.0,)),
+               "mix": (tuple(sizes or sources.CONFIG4_SIZES), tuple(weights or sources.CONFIG4_WEIGHTS))}
+    for name, (szs, wts) in streams.items():
+        pool = source_pool(szs, 4, seed=4, dtype=dtype)
+        ex = GpuExecutor(dtype=dtype)
+
+        def make(reqs_spec):
+            out = []
+            for i, (t, nn) in enumerate(reqs_spec):
+                S = pool[nn][i % len(pool[nn])]
+                out.append(Request(i, (nn, nn, nn), (1.0 / nn,) * 3, S, arrival=t))
+            return out
+
+        # warm plans and kernels
+        warm = Server(ex, budget, max_inflight=max_inflight)
+        warm.run_trace(make([(0.0, s) for s in szs for _ in range(2)]), realtime=False)
+        ex.synchronize()
+        # closed loop: all requests present at t = 0
+        trace = sources.config4_trace(rate_hz=0, count=count, sizes=szs, weights=wts)
+        srv = Server(ex, budget, max_inflight=max_inflight)
+        t0 = time.perf_counter()
+        fin = srv.run_trace(make([(0.0, r.n) for r in trace]), realtime=False)
+        ex.synchronize()
+        wall = time.perf_counter() - t0
+        sat = summarize(fin, wall)
+        log(f"[serve] {name}: saturation {sat['solves_per_s']:.0f} solves/s, {srv.launches} launches, "
+            f"max batch {srv.max_batch}")
+        # open loop: Poisson arrivals at 0.7 x saturation
+        rate = 0.7 * sat["solves_per_s"]
+        trace = sources.config4_trace(rate_hz=rate, count=count, sizes=szs, weights=wts)
+        srv = Server(ex, budget, max_inflight=max_inflight)
+        t0 = time.perf_counter()
+        fin = srv.run_trace(make([(r.arrival, r.n) for r in trace]), realtime=True)
+        ex.synchronize()
+        wall = time.perf_counter() - t0
+        op = summarize(fin, wall)
+        log(f"[serve] {name}: Poisson {rate:.0f}/s: p50 {op['latency_ms_p50']:.3f} ms, "
+            f"p99 {op['latency_ms_p99']:.3f} ms")
+        results[name] = {"sizes": list(szs), "weights": list(wts), "saturation": sat,
+                         "poisson_rate_hz": rate, "poisson": op, "budget_bytes": budget,
+                         "max_inflight": max_inflight}
+        for lst in ex.pool.values():
+            for ws in lst:
+                ws.close()
+        for p in ex.plans.values():
+            p.close()
+    return results

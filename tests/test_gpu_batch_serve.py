@@ -1,0 +1,145 @@
+"""Grouped (batched) launches and the serving loop on the GPU.
+
+* config 3 layout: 64 Gaussian-blob sources with n drawn from {32,48,64,96,128},
+  solved in grouped launches; every result is bit-identical to the same source
+  solved alone, and matches the FP64 oracle within the FP32 bar.
+* the serving loop: requests of mixed sizes admitted as slots and memory free
+  up give, bit for bit, the result of solving each alone; a small memory budget
+  still serves everything without exceeding it.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import norms
+from paper_1106_0557_amd import sources
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_1106_0557_amd import _lib
+
+    _lib.load()
+    yield
+
+
+def test_config3_grouped_launches_match_single_solves_and_oracle():
+    import paper_1106_0557_amd as ps
+
+    say("[config3] 64 sources, grouped launches")
+    batch = sources.config3(device="cuda")
+    plans = {}
+    ws, S, P = [], [], []
+    for n, src in batch:
+        if n not in plans:
+            plans[n] = ps.Plan(n, n, n, h=1.0 / n, dtype=torch.float32)
+        ws.append(plans[n].workspace())
+        S.append(src.to(torch.float32).contiguous())
+        P.append(torch.empty_like(S[-1]))
+    ps.solve_batched(ws, S, P)
+    torch.cuda.synchronize()
+    checked = set()
+    for i, (n, src) in enumerate(batch):
+        alone = plans[n].solve(S[i])
+        torch.cuda.synchronize()
+        assert torch.equal(alone, P[i]), f"problem {i} (n={n}) differs between batch and single solve"
+        if n not in checked or i % 16 == 0:  # oracle check on each size and a few more
+            checked.add(n)
+            ref = oracle.solve_fft(src.cpu().numpy(), 1.0 / n)
+            r = norms.report(P[i].double().cpu().numpy(), ref)
+            say(f"  problem {i} n={n}: {r}")
+            assert r["rel_l2"] <= 1e-5
+    for w in ws:
+        w.close()
+    for p in plans.values():
+        p.close()
+
+
+def test_mixed_precision_batch_matches_single():
+    import paper_1106_0557_amd as ps
+
+    say("[mixed precision batch]")
+    cases = [((32, 24, 16), torch.float32), ((32, 24, 16), torch.float64), ((48, 48, 48), torch.float64),
+             ((16, 36, 20), torch.float32)]
+    ws, S, P, plans = [], [], [], []
+    for k, (n, dt) in enumerate(cases):
+        pl = ps.Plan(*n, h=(0.1, 0.2, 0.3), dtype=dt)
+        plans.append(pl)
+        ws.append(pl.workspace())
+        S.append(sources.random_field(n, seed=k).to("cuda", dt))
+        P.append(torch.empty_like(S[-1]))
+    ps.solve_batched(ws, S, P)
+    torch.cuda.synchronize()
+    for k, (n, dt) in enumerate(cases):
+        alone = plans[k].solve(S[k])
+        torch.cuda.synchronize()
+        assert torch.equal(alone, P[k])
+        ref = oracle.solve_fft(S[k].double().cpu().numpy(), (0.1, 0.2, 0.3))
+        tol = 1e-12 if dt == torch.float64 else 1e-5
+        assert norms.rel_l2(P[k].double().cpu().numpy(), ref) <= tol
+
+
+def _serve(reqs, budget, max_inflight):
+    from paper_1106_0557_amd.serve import GpuExecutor, Server
+
+    ex = GpuExecutor(dtype=torch.float32)
+    srv = Server(ex, budget_bytes=budget, max_inflight=max_inflight)
+    fin = srv.run_trace(reqs, realtime=False)
+    ex.synchronize()
+    return ex, srv, fin
+
+
+def test_served_results_equal_alone_in_the_mix():
+    import paper_1106_0557_amd as ps
+    from paper_1106_0557_amd.serve import Request
+
+    say("[serve] mixed sizes, results alone vs in the mix")
+    rng = np.random.default_rng(41)
+    sizes = [int(rng.choice([32, 48, 64, 96])) for _ in range(40)]
+    reqs = []
+    for i, n in enumerate(sizes):
+        S = sources.blob_field(n, sources.draw_blobs(rng, 8), device="cuda").to(torch.float32)
+        reqs.append(Request(i, (n, n, n), (1.0 / n,) * 3, S))
+    ex, srv, fin = _serve(reqs, budget=1 << 34, max_inflight=7)
+    assert len(fin) == len(reqs) and all(r.done and not r.rejected for r in fin)
+    say(f"  {srv.launches} launches, max group {srv.max_batch}")
+    for r in fin:
+        alone = ex.plans[ex.key(r)].solve(r.S)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, r.phi), f"request {r.index} (n={r.n[0]}) differs in the mix"
+    r = fin[3]
+    ref = oracle.solve_fft(r.S.double().cpu().numpy(), r.h)
+    assert norms.rel_l2(r.phi.double().cpu().numpy(), ref) <= 1e-5
+
+
+def test_served_small_budget_defers_but_serves_all():
+    from paper_1106_0557_amd.serve import Request
+
+    say("[serve] small memory budget")
+    import paper_1106_0557_amd as ps
+
+    n = 64
+    one = ps.workspace_bytes(n, n, n, torch.float32) + n**3 * 4
+    reqs = [Request(i, (n, n, n), (1.0 / n,) * 3, sources.random_field(n, seed=i).to("cuda", torch.float32))
+            for i in range(12)]
+    big = Request(99, (128, 128, 128), (1 / 128,) * 3, torch.zeros((128, 128, 128), device="cuda"))
+    ex, srv, fin = _serve(reqs + [big], budget=2 * one + 1024, max_inflight=8)
+    assert srv.max_used <= srv.budget
+    assert [r.index for r in fin if r.rejected] == [99]
+    served = [r for r in fin if not r.rejected]
+    assert len(served) == 12
+    for r in served[:3]:
+        ref = oracle.solve_fft(r.S.double().cpu().numpy(), r.h)
+        assert norms.rel_l2(r.phi.double().cpu().numpy(), ref) <= 1e-5
