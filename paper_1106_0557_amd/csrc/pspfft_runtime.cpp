@@ -89,6 +89,24 @@ int xcd_remap_mode(int mode) {
     return (mode >= 0 && mode < 5) ? modes[mode] : 0;
 }
 
+// Lines per workgroup of each pass; PSPFFT_TILE="a,b,c,d,e" overrides (powers of two).
+int line_tile(int mode, int dflt) {
+    static int v[5] = {-1, -1, -1, -1, -1};
+    if (v[0] < 0) {
+        for (int i = 0; i < 5; ++i) v[i] = 0;
+        if (const char *e = std::getenv("PSPFFT_TILE")) {
+            int i = 0;
+            for (const char *q = e; *q && i < 5; ++i) {
+                v[i] = std::atoi(q);
+                while (*q && *q != ',') ++q;
+                if (*q == ',') ++q;
+            }
+        }
+    }
+    const int o = (mode >= 0 && mode < 5) ? v[mode] : 0;
+    return (o > 0 && (o & (o - 1)) == 0) ? o : dflt;
+}
+
 size_t real_size(pspfft_precision p) { return p == PSPFFT_FP32 ? 4 : 8; }
 size_t cplx_size(pspfft_precision p) { return 2 * real_size(p); }
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -293,7 +311,7 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
         });
         // Column passes: 128-byte rows of complex values per wavefront row.
         // Row passes: enough rows per workgroup for 256-thread groups.
-        const int tile_target = row ? (prec == 0 ? 32 : 16) : (prec == 0 ? 16 : 8);
+        const int tile_target = line_tile(mode, row ? (prec == 0 ? 32 : 16) : (prec == 0 ? 16 : 8));
         const int bmax = pspfft::max_block_for(prec, E);
         const int csz = prec == 0 ? 8 : 16;
         for (size_t c0 = 0; c0 < idx.size(); c0 += pspfft::kMaxProblems) {

@@ -69,6 +69,7 @@ class GpuExecutor:
         # default priority streams only
         self.streams = [torch.cuda.Stream(device=device) for _ in range(NUM_PASSES)]
         self._last_step_event = None
+        self._used = []
 
     # ------------------------------------------------------------- plans
     def key(self, req: Request):
@@ -127,18 +128,20 @@ class GpuExecutor:
 
     # ------------------------------------------------------------ launches
     def begin_step(self) -> None:
-        if self._last_step_event is not None:
-            for s in self.streams:
-                s.wait_event(self._last_step_event)
+        self._used = []
 
     def run_pass(self, p: int, reqs: Sequence[Request]) -> None:
+        s = self.streams[p]
+        if self._last_step_event is not None:
+            s.wait_event(self._last_step_event)  # after everything of the previous step
+        self._used.append(s)
         ws = [r._ws for r in reqs]
-        self.ps.pass_batched(p, ws, S=[r.S for r in reqs], Phi=[r.phi for r in reqs], stream=self.streams[p])
+        self.ps.pass_batched(p, ws, S=[r.S for r in reqs], Phi=[r.phi for r in reqs], stream=s)
 
     def end_step(self):
         torch = self.torch
-        cur = self.streams[0]
-        for s in self.streams[1:]:
+        cur = self._used[0]
+        for s in self._used[1:]:  # join the streams this step used
             ev = torch.cuda.Event()
             ev.record(s)
             cur.wait_event(ev)
@@ -168,7 +171,7 @@ class Server:
     device, ``max_steps_ahead`` the scheduler steps enqueued but not finished.
     """
 
-    def __init__(self, executor, budget_bytes: int, max_inflight: int = 64, max_steps_ahead: int = 2,
+    def __init__(self, executor, budget_bytes: int, max_inflight: int = 64, max_steps_ahead: int = 4,
                  clock: Callable[[], float] = time.perf_counter):
         self.ex = executor
         self.budget = int(budget_bytes)
