@@ -38,8 +38,9 @@
  *
  * Supported sizes.  Each of nx, ny, nz must be 2^a * o with o in {1, 3, 5, 9};
  * ny, nz >= 8 (o = 1), 10 (o = 5), 12 (o = 3) or 18 (o = 9); nx, transformed in
- * packed real form, >= 16, 20, 24 or 36 respectively; every n <= 2048 in FP32
- * and <= 1152 in FP64.  Other sizes return PSPFFT_ERR_UNSUPPORTED_SIZE.
+ * packed real form, >= 16, 20, 24 or 36 respectively; ny, nz <= 2048 and
+ * nx <= 4096 in FP32, ny, nz <= 1152 and nx <= 2304 in FP64.  Other sizes
+ * return PSPFFT_ERR_UNSUPPORTED_SIZE.
  * S and Phi must be aligned to two reals (8 bytes FP32, 16 bytes FP64).
  */
 #ifndef PSPFFT_H

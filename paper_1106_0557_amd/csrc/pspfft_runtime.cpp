@@ -132,8 +132,10 @@ int axis_len(int axis, int n) { return axis == 0 ? n : 2 * n; }
 
 int max_n(pspfft_precision p) { return p == PSPFFT_FP32 ? 2048 : 1152; }
 
+// The packed x transform has length n, so x may be twice as long as y and z.
 bool size_ok(int axis, int n, pspfft_precision p) {
-    return n >= 1 && n <= max_n(p) && family_of_len(axis_len(axis, n)) != 0;
+    const int lim = axis == 0 ? 2 * max_n(p) : max_n(p);
+    return n >= 1 && n <= lim && family_of_len(axis_len(axis, n)) != 0;
 }
 
 bool sizes_ok(int nx, int ny, int nz, pspfft_precision p) {

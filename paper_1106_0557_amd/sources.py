@@ -54,11 +54,12 @@ def _sub_offsets(sub, device):
     return (torch.arange(sub, dtype=torch.float64, device=device) + 0.5) / sub - 0.5
 
 
-def _ellipsoid_fraction(n, h, origin, centre, semi, sub, device):
+def _ellipsoid_fraction(n, h, origin, centre, semi, sub, device, zchunk=64):
     """Fraction of the ``sub^3`` sample points of each cell with sum((x-c)/semi)^2 <= 1.
 
     ``sub = 1`` is point sampling at the cell centre; larger ``sub`` approximates the
-    volume fraction of the cell inside the body.
+    volume fraction of the cell inside the body.  Computed in slabs of ``zchunk``
+    planes to bound temporary memory on large meshes.
     """
     x, y, z = cell_centres(n, h, origin=origin, device=device)
     hx, hy, hz = _as3(h)
@@ -70,10 +71,12 @@ def _ellipsoid_fraction(n, h, origin, centre, semi, sub, device):
     qz = (((z[:, None] + off[None, :] * hz) - cz) / az) ** 2
     nx, ny, nz = x.numel(), y.numel(), z.numel()
     acc = torch.zeros((nz, ny, nx), dtype=torch.float64, device=device)
-    for k in range(sub):
-        for j in range(sub):
-            q = qz[:, k][:, None, None, None] + qy[:, j][None, :, None, None] + qx[None, None, :, :]
-            acc += (q <= 1.0).to(torch.float64).sum(dim=-1)
+    for z0 in range(0, nz, zchunk):
+        z1 = min(nz, z0 + zchunk)
+        for k in range(sub):
+            for j in range(sub):
+                q = qz[z0:z1, k][:, None, None, None] + qy[:, j][None, :, None, None] + qx[None, None, :, :]
+                acc[z0:z1] += (q <= 1.0).to(torch.float64).sum(dim=-1)
     return acc / float(sub ** 3)
 
 

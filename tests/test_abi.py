@@ -57,8 +57,8 @@ def test_supported_sizes_y_z(lib, n, ok):
 
 
 @pytest.mark.parametrize("n,ok", [(16, True), (20, True), (24, True), (36, True), (32, True), (40, True),
-                                  (48, True), (72, True), (128, True), (2048, True), (8, False), (10, False),
-                                  (12, False), (18, False), (6, False), (4096, False)])
+                                  (48, True), (72, True), (128, True), (2048, True), (4096, True), (2304, True),
+                                  (8, False), (10, False), (12, False), (18, False), (6, False), (8192, False)])
 def test_supported_sizes_x(lib, n, ok):
     """x uses the packed real transform of length n, so its minimum sizes are twice those of y, z."""
     assert (lib.pspfft_workspace_bytes(n, 16, 16, 0) > 0) == ok
@@ -73,8 +73,10 @@ def test_workspace_bytes_formula(lib):
             assert lib.pspfft_workspace_bytes(nx, ny, nz, prec) == want
     assert lib.pspfft_workspace_bytes(16, 16, 16, 7) == 0
     # FP64 has a smaller maximum size
-    assert lib.pspfft_workspace_bytes(2048, 8, 8, 0) > 0
-    assert lib.pspfft_workspace_bytes(2048, 8, 8, 1) == 0
+    assert lib.pspfft_workspace_bytes(16, 2048, 8, 0) > 0
+    assert lib.pspfft_workspace_bytes(16, 2048, 8, 1) == 0
+    assert lib.pspfft_workspace_bytes(2304, 8, 8, 1) > 0
+    assert lib.pspfft_workspace_bytes(4096, 8, 8, 1) == 0
 
 
 def _create(lib, n, h, prec=0):
