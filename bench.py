@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per served trace")
+    ap.add_argument("--no-large", action="store_true", help="skip the 512^3 single-solve measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -213,6 +214,46 @@ def main():
     solves64 = R / wall64
     eff64 = algorithmic_bytes(n, 8) * solves64 / 1e9
 
+    # --------------------------------- single large solve, 512^3 (context)
+    large = None
+    if not args.no_large:
+        nl = 512
+        log(f"[bench] single large solve n={nl}")
+        _, hl, Sl = sources.config5(n=nl, device="cuda")
+        large = {"n": nl, "padded": 2 * nl}
+        for dt, tag in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+            t0 = time.perf_counter()
+            pl = ps.Plan(nl, nl, nl, h=hl, dtype=dt)
+            torch.cuda.synchronize()
+            t_plan = time.perf_counter() - t0
+            src = Sl.to(dt)
+            out = torch.empty_like(src)
+            pl.solve(src, out=out)
+            torch.cuda.synchronize()
+            reps = 10
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+            ev[0].record(stream)
+            for i in range(reps):
+                pl.solve(src, out=out)
+                ev[i + 1].record(stream)
+            torch.cuda.synchronize()
+            lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+            ms = sum(lat) / reps
+            large[tag] = {"ms_per_solve": round(ms, 3), "solves_per_s": round(1e3 / ms, 2),
+                          "effective_GBps": round(algorithmic_bytes(nl, 4 if tag == "fp32" else 8) / (ms * 1e-3) / 1e9, 1),
+                          "plan_create_s": round(t_plan, 3)}
+            if tag == "fp32":
+                out32 = out.double()
+            else:
+                d = out32 - out
+                large["fp32_vs_fp64"] = {"rel_l2": float(d.norm() / out.norm()),
+                                         "rel_max": float(d.abs().max() / out.abs().max())}
+            pl.close()
+            del src, out
+        del Sl, out32
+        torch.cuda.empty_cache()
+        log(f"[bench] large: {large}")
+
     # ----------------------------------------------- serving loop (Poisson)
     serve = None
     if not args.no_serve:
@@ -291,6 +332,7 @@ def main():
                      "traffic": traffic},
         "cpu_baseline": cpu,
         "served": serve,
+        "single_large_solve": large,
         "kernel_source_hash": source_hash(),
     }
     print(json.dumps(result), flush=True)
