@@ -88,7 +88,7 @@ enum PassMode { X_FWD = 0, Y_FWD = 1, Z_CONV = 2, Y_INV = 3, X_INV = 4 };
 // Column passes keep element (line c, position P) at P*(tile+1) + c; row passes
 // at c*S + P + P/16, with S chosen so that the NB-lane chunks of consecutive
 // rows fall on different banks.
-__host__ __device__ inline int row_stride(int L, int NB, int csz) {
+__host__ __device__ constexpr int row_stride(int L, int NB, int csz) {
     int S = L + (L >> 4);
     const int chunk = NB * csz;
     if (chunk < 256) {
@@ -97,7 +97,7 @@ __host__ __device__ inline int row_stride(int L, int NB, int csz) {
     }
     return S;
 }
-__host__ __device__ inline int data_elems(bool row, int L, int NB, int block, int csz) {
+__host__ __device__ constexpr int data_elems(bool row, int L, int NB, int block, int csz) {
     const int tile = block / NB;
     return row ? tile * row_stride(L, NB, csz) : L * (tile + 1);
 }
@@ -106,6 +106,12 @@ inline int pass_axis(int mode) { return mode == X_FWD || mode == X_INV ? 0 : (mo
 
 // Largest workgroup per (precision, radix family), chosen so that the E
 // registers per thread fit without spilling.
+// Default lines per workgroup: column passes take 128-byte row segments of
+// complex values, row passes enough rows for 256-thread groups.
+__host__ __device__ constexpr int default_tile(int prec, bool row) {
+    return row ? (prec == 0 ? 32 : 16) : (prec == 0 ? 16 : 8);
+}
+
 __host__ __device__ constexpr int max_block_for(int prec, int E) {
     return prec == 0 ? (E == 16 ? 1024 : (E <= 24 ? 512 : 256)) : (E == 16 ? 512 : 256);
 }
@@ -113,8 +119,8 @@ __host__ __device__ constexpr int max_block_for(int prec, int E) {
 // Launchers: one per (precision, family), defined in pass_<prec>_e<E>.hip.
 // K is the radix of the last stage of the pass axis (1 for a single stage).
 #define PSPFFT_DECLARE_FAMILY(NAME)                                                                 \
-    hipError_t NAME(int mode, int K, const LaunchArgs &args, int grid, int block, size_t lds,       \
-                    hipStream_t stream);
+    hipError_t NAME(int mode, int K, bool fix, const LaunchArgs &args, int grid, int block,         \
+                    size_t lds, hipStream_t stream);
 PSPFFT_DECLARE_FAMILY(launch_f32_e16)
 PSPFFT_DECLARE_FAMILY(launch_f32_e20)
 PSPFFT_DECLARE_FAMILY(launch_f32_e24)
@@ -125,18 +131,18 @@ PSPFFT_DECLARE_FAMILY(launch_f64_e24)
 PSPFFT_DECLARE_FAMILY(launch_f64_e36)
 #undef PSPFFT_DECLARE_FAMILY
 
-inline hipError_t launch_pass(int mode, int prec, int E, int K, const LaunchArgs &args, int grid, int block,
-                              size_t lds, hipStream_t stream) {
+inline hipError_t launch_pass(int mode, int prec, int E, int K, bool fix, const LaunchArgs &args, int grid,
+                              int block, size_t lds, hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
     switch (prec * 100 + E) {
-        case 16: return launch_f32_e16(mode, K, args, grid, block, lds, stream);
-        case 20: return launch_f32_e20(mode, K, args, grid, block, lds, stream);
-        case 24: return launch_f32_e24(mode, K, args, grid, block, lds, stream);
-        case 36: return launch_f32_e36(mode, K, args, grid, block, lds, stream);
-        case 116: return launch_f64_e16(mode, K, args, grid, block, lds, stream);
-        case 120: return launch_f64_e20(mode, K, args, grid, block, lds, stream);
-        case 124: return launch_f64_e24(mode, K, args, grid, block, lds, stream);
-        case 136: return launch_f64_e36(mode, K, args, grid, block, lds, stream);
+        case 16: return launch_f32_e16(mode, K, fix, args, grid, block, lds, stream);
+        case 20: return launch_f32_e20(mode, K, fix, args, grid, block, lds, stream);
+        case 24: return launch_f32_e24(mode, K, fix, args, grid, block, lds, stream);
+        case 36: return launch_f32_e36(mode, K, fix, args, grid, block, lds, stream);
+        case 116: return launch_f64_e16(mode, K, fix, args, grid, block, lds, stream);
+        case 120: return launch_f64_e20(mode, K, fix, args, grid, block, lds, stream);
+        case 124: return launch_f64_e24(mode, K, fix, args, grid, block, lds, stream);
+        case 136: return launch_f64_e36(mode, K, fix, args, grid, block, lds, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -28,13 +28,17 @@
 
 namespace pspfft {
 
-template <typename T, int E, int DIR, bool ROW>
+// CNB, CLDSW: threads per line and LDS stride when known at compile time (a
+// two-stage line, L = E*K, in a workgroup of the default tile), else 0.
+template <typename T, int E, int DIR, bool ROW, int CNB = 0, int CLDSW = 0>
 struct LineFFT {
     static constexpr int M = E & -E;  // radix of the middle stages
 
     // LDS layout: column passes keep (line c, position P) at P*ldsw + c with
     // ldsw = tile + 1; row passes at c*ldsw + P + P/16 with ldsw = row_stride().
-    static __device__ __forceinline__ void gather(cx<T> *v, const cx<T> *lds, int ldsw, int c, int t, int NB) {
+    static __device__ __forceinline__ void gather(cx<T> *v, const cx<T> *lds, int ldsw_, int c, int t, int NB_) {
+        const int NB = CNB ? CNB : NB_;
+        const int ldsw = CLDSW ? CLDSW : ldsw_;
         if constexpr (ROW) {
             const cx<T> *row = lds + c * ldsw;
 #pragma unroll
@@ -55,16 +59,20 @@ struct LineFFT {
     // twiddle table.  TW: multiply by twiddles (every stage but the first).
     // TO_LDS: scatter the outputs to their Stockham positions in LDS; otherwise
     // (last stage) they land in the thread's own positions, in registers.
-    template <int R, bool TW, bool TO_LDS>
-    static __device__ __forceinline__ void stage(cx<T> *v, int Ns, uint32_t mg, const cx<T> *tw, cx<T> *lds,
-                                                 int ldsw, int c, int t, int NB) {
+    template <int R, bool TW, bool TO_LDS, int CNS = 0>
+    static __device__ __forceinline__ void stage(cx<T> *v, int Ns_, uint32_t mg, const cx<T> *tw, cx<T> *lds,
+                                                 int ldsw_, int c, int t, int NB_) {
         constexpr int NBF = E / R;
+        const int NB = CNB ? CNB : NB_;
+        const int ldsw = CLDSW ? CLDSW : ldsw_;
+        const int Ns = CNS ? CNS : Ns_;
         sfor<0, NBF>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             const int b = t + NB * i;
             int q = b, k = 0;
             if constexpr (TW) {
-                q = static_cast<int>(__umulhi(static_cast<uint32_t>(b), mg));
+                if constexpr (CNS != 0) q = b / CNS;
+                else q = static_cast<int>(__umulhi(static_cast<uint32_t>(b), mg));
                 k = b - q * Ns;
             }
             cx<T> x[R];
@@ -114,9 +122,17 @@ struct LineFFT {
     template <int K>
     static __device__ __forceinline__ void run(cx<T> *v, const AxisPlan &ax, cx<T> *lds, int ldsw,
                                                const cx<T> *twl, int c, int t) {
-        const int NB = ax.NB;
+        const int NB = CNB ? CNB : ax.NB;
         if constexpr (K == 1) {
             stage<E, false, false>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
+        } else if constexpr (CNB != 0) {
+            // two stages, radix E then K: the second has Ns = E and its twiddles
+            // follow the E - 1 entries of the first
+            __syncthreads();  // earlier readers of LDS are done
+            stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
+            __syncthreads();
+            gather(v, lds, ldsw, c, t, NB);
+            stage<K, true, false, E>(v, E, 0u, twl + (E - 1), lds, ldsw, c, t, NB);
         } else {
             __syncthreads();  // earlier readers of LDS are done
             stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
@@ -140,14 +156,20 @@ __device__ __forceinline__ void copy_to_lds(cx<T> *dst, const void *src, int cou
     for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = s[i];
 }
 
-template <typename T, int E, int K, int MODE>
+// FIX: every problem of the launch has a two-stage line (L = E*K, NB = K) and the
+// workgroup holds the default number of lines, so the geometry is compile-time.
+template <typename T, int E, int K, int MODE, bool FIX>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pass_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
     constexpr bool ROW = (MODE == X_FWD || MODE == X_INV);
     constexpr int H = E / 2;  // registers m < H hold the first half of the line
-    using FFT_F = LineFFT<T, E, -1, ROW>;
-    using FFT_I = LineFFT<T, E, +1, ROW>;
+    constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
+    constexpr int FTILE = default_tile(sizeof(T) == 4 ? 0 : 1, ROW);
+    constexpr int CNB = FIX ? K : 0;
+    constexpr int CLDSW = FIX ? (ROW ? row_stride(E * K, K, CSZ) : FTILE + 1) : 0;
+    using FFT_F = LineFFT<T, E, -1, ROW, CNB, CLDSW>;
+    using FFT_I = LineFFT<T, E, +1, ROW, CNB, CLDSW>;
 
     // XCD-aware order: hardware hands consecutive workgroups to the 8 XCDs in
     // turn; renumber so that each XCD works through a contiguous range of the
@@ -174,10 +196,10 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr int axis = ROW ? 0 : (MODE == Z_CONV ? 2 : 1);
     const AxisPlan &ax = pl.ax[axis];
     const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
-    const int NB = ax.NB;
-    const int L = ax.L;
-    const int block = static_cast<int>(blockDim.x);
-    const int tile = block / NB;  // lines per workgroup (power of two)
+    const int NB = FIX ? K : ax.NB;
+    const int L = FIX ? E * K : ax.L;
+    const int block = FIX ? FTILE * K : static_cast<int>(blockDim.x);
+    const int tile = FIX ? FTILE : block / NB;  // lines per workgroup (power of two)
     const int tid = threadIdx.x;
     int c, t;
     if constexpr (ROW) {  // rows are contiguous in memory: consecutive lanes walk along a row
@@ -187,8 +209,8 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         c = tid & (tile - 1);
         t = tid >> __builtin_ctz(tile);
     }
-    const int ldsw = ROW ? row_stride(L, NB, static_cast<int>(sizeof(cx<T>))) : tile + 1;
-    cx<T> *twl = lds + data_elems(ROW, L, NB, block, static_cast<int>(sizeof(cx<T>)));
+    const int ldsw = FIX ? CLDSW : (ROW ? row_stride(L, NB, CSZ) : tile + 1);
+    cx<T> *twl = lds + (FIX ? data_elems(ROW, E * K, K, FTILE * K, CSZ) : data_elems(ROW, L, NB, block, CSZ));
     copy_to_lds<T>(twl, ax.tw, ax.ntw);
 
     const bool nyq = local >= sg.wg_main;
@@ -334,9 +356,9 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             else v[m] = cx<T>{T(0), T(0)};
         }
         if constexpr (MODE == Y_FWD) {
-            FFT_F::template run<K>(v, ax, lds, tile + 1, twl, c, t);
+            FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
         } else if constexpr (MODE == Y_INV) {
-            FFT_I::template run<K>(v, ax, lds, tile + 1, twl, c, t);
+            FFT_I::template run<K>(v, ax, lds, ldsw, twl, c, t);
         } else {
             // Spectrum values for this thread's kz positions, fetched with the line
             // so that both memory latencies overlap.  G~ is even in ky and kz: octant
@@ -355,10 +377,10 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 if (active) gv[m] = m < H ? glo[m * gstep] : ghi[(E - m) * gstep];
                 else gv[m] = T(0);
             }
-            FFT_F::template run<K>(v, ax, lds, tile + 1, twl, c, t);
+            FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = scale(v[m], gv[m]);
-            FFT_I::template run<K>(v, ax, lds, tile + 1, twl, c, t);
+            FFT_I::template run<K>(v, ax, lds, ldsw, twl, c, t);
         }
         // Inverse transforms keep only the first half (m < H).
         constexpr int nstore = (MODE == Y_FWD) ? E : H;
@@ -369,10 +391,10 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     }
 }
 
-template <typename T, int E, int K, int MODE>
+template <typename T, int E, int K, int MODE, bool FIX>
 hipError_t launch_kernel(const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
     static bool attr_set = false;
-    auto fn = pass_kernel<T, E, K, MODE>;
+    auto fn = pass_kernel<T, E, K, MODE, FIX>;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -383,33 +405,42 @@ hipError_t launch_kernel(const LaunchArgs &args, int grid, int block, size_t lds
     return hipGetLastError();
 }
 
-template <typename T, int E, int K>
+template <typename T, int E, int K, bool FIX>
 hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
     switch (mode) {
-        case X_FWD: return launch_kernel<T, E, K, X_FWD>(args, grid, block, lds, stream);
-        case Y_FWD: return launch_kernel<T, E, K, Y_FWD>(args, grid, block, lds, stream);
-        case Z_CONV: return launch_kernel<T, E, K, Z_CONV>(args, grid, block, lds, stream);
-        case Y_INV: return launch_kernel<T, E, K, Y_INV>(args, grid, block, lds, stream);
-        case X_INV: return launch_kernel<T, E, K, X_INV>(args, grid, block, lds, stream);
+        case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
+        case Y_FWD: return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
+        case Z_CONV: return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
+        case Y_INV: return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
+        case X_INV: return launch_kernel<T, E, K, X_INV, FIX>(args, grid, block, lds, stream);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <typename T, int E, int K>
+hipError_t launch_fix(int mode, bool fix, const LaunchArgs &args, int grid, int block, size_t lds,
+                      hipStream_t stream) {
+    if constexpr (K > 1) {
+        if (fix) return launch_mode<T, E, K, true>(mode, args, grid, block, lds, stream);
+    }
+    return launch_mode<T, E, K, false>(mode, args, grid, block, lds, stream);
 }
 
 // All last-stage radices a family can have: 1 (single stage) and the powers of
 // two up to the middle radix.
 template <typename T, int E>
-hipError_t launch_family(int mode, int K, const LaunchArgs &args, int grid, int block, size_t lds,
+hipError_t launch_family(int mode, int K, bool fix, const LaunchArgs &args, int grid, int block, size_t lds,
                          hipStream_t stream) {
     constexpr int M = E & -E;
     switch (K) {
-        case 1: return launch_mode<T, E, 1>(mode, args, grid, block, lds, stream);
-        case 2: return launch_mode<T, E, 2>(mode, args, grid, block, lds, stream);
-        case 4: return launch_mode<T, E, 4>(mode, args, grid, block, lds, stream);
+        case 1: return launch_fix<T, E, 1>(mode, fix, args, grid, block, lds, stream);
+        case 2: return launch_fix<T, E, 2>(mode, fix, args, grid, block, lds, stream);
+        case 4: return launch_fix<T, E, 4>(mode, fix, args, grid, block, lds, stream);
         case 8:
-            if constexpr (M >= 8) return launch_mode<T, E, 8>(mode, args, grid, block, lds, stream);
+            if constexpr (M >= 8) return launch_fix<T, E, 8>(mode, fix, args, grid, block, lds, stream);
             else return hipErrorInvalidValue;
         case 16:
-            if constexpr (M >= 16) return launch_mode<T, E, 16>(mode, args, grid, block, lds, stream);
+            if constexpr (M >= 16) return launch_fix<T, E, 16>(mode, fix, args, grid, block, lds, stream);
             else return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
@@ -420,8 +451,8 @@ hipError_t launch_family(int mode, int K, const LaunchArgs &args, int grid, int 
 // One translation unit per (precision, family) keeps compiles parallel.
 #define PSPFFT_FAMILY(T, E, NAME)                                                                   \
     namespace pspfft {                                                                              \
-    hipError_t NAME(int mode, int K, const LaunchArgs &args, int grid, int block, size_t lds,       \
-                    hipStream_t stream) {                                                           \
-        return launch_family<T, E>(mode, K, args, grid, block, lds, stream);                        \
+    hipError_t NAME(int mode, int K, bool fix, const LaunchArgs &args, int grid, int block,         \
+                    size_t lds, hipStream_t stream) {                                               \
+        return launch_family<T, E>(mode, K, fix, args, grid, block, lds, stream);                   \
     }                                                                                               \
     }

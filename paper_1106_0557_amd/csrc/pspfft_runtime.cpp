@@ -313,7 +313,7 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
         });
         // Column passes: 128-byte rows of complex values per wavefront row.
         // Row passes: enough rows per workgroup for 256-thread groups.
-        const int tile_target = line_tile(mode, row ? (prec == 0 ? 32 : 16) : (prec == 0 ? 16 : 8));
+        const int tile_target = line_tile(mode, pspfft::default_tile(prec, row));
         const int bmax = pspfft::max_block_for(prec, E);
         const int csz = prec == 0 ? 8 : 16;
         for (size_t c0 = 0; c0 < idx.size(); c0 += pspfft::kMaxProblems) {
@@ -378,7 +378,11 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
             const int grid = static_cast<int>((wg + align - 1) / align * align);
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d: %d problems in %d segments, %ld workgroups of %d threads, %zu B LDS",
                        mode, prec, E, K, args.count, args.nseg, wg, block, lds);
-            if (pspfft::launch_pass(mode, prec, E, K, args, grid, block, lds, stream) != hipSuccess)
+            // compile-time geometry when every line has two stages (L = E*K) and the
+            // workgroup holds the default number of lines
+            bool fix = K > 1 && block == pspfft::default_tile(prec, row) * K;
+            for (size_t j = c0; j < c1 && fix; ++j) fix = plans[idx[j]]->host.ax[axis].nst == 2;
+            if (pspfft::launch_pass(mode, prec, E, K, fix, args, grid, block, lds, stream) != hipSuccess)
                 return PSPFFT_ERR_DEVICE;
         }
     }
