@@ -139,21 +139,25 @@ def main():
     torch.cuda.synchronize()
 
     # --------------------------------------------- FP32 served batch (timed)
-    pass_names = ps.PASS_NAMES
+    # a fused plan does its x and y transforms in the x passes and skips the y passes
+    active = plan32.active_passes
+    pass_names = {p: ps.PASS_NAMES[p] for p in active}
+    if plan32.fused:
+        pass_names[ps.PASS_X_FWD], pass_names[ps.PASS_X_INV] = "xy_fwd", "yx_inv"
 
     def step(evs=None):
-        for p in range(5):
+        for i, p in enumerate(active):
             if evs is not None:
-                evs[p].record(stream)
+                evs[i].record(stream)
             ps.pass_batched(p, ws, S=S_list, Phi=P_list, stream=stream)
         if evs is not None:
-            evs[5].record(stream)
+            evs[len(active)].record(stream)
 
     log(f"[bench] warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ev_sets = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    ev_sets = [[torch.cuda.Event(enable_timing=True) for _ in range(len(active) + 1)] for _ in range(args.steps)]
     log(f"[bench] timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -161,17 +165,17 @@ def main():
         step(ev_sets[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_pass_ms = [[evs[p].elapsed_time(evs[p + 1]) for evs in ev_sets] for p in range(5)]
-    step_ms = [evs[0].elapsed_time(evs[5]) for evs in ev_sets]
+    per_pass_ms = {p: [evs[i].elapsed_time(evs[i + 1]) for evs in ev_sets] for i, p in enumerate(active)}
+    step_ms = [evs[0].elapsed_time(evs[len(active)]) for evs in ev_sets]
     solves32 = B * args.steps / wall
     bytes32 = algorithmic_bytes(n, 4)
     eff32 = bytes32 * solves32 / 1e9
-    avg_pass = [sum(v) / len(v) for v in per_pass_ms]
-    dom = max(range(5), key=lambda p: avg_pass[p])
+    avg_pass = {p: sum(v) / len(v) for p, v in per_pass_ms.items()}
+    dom = max(active, key=lambda p: avg_pass[p])
     dom_bytes = plan32.pass_bytes(dom) * B
     dom_gbs = dom_bytes / (avg_pass[dom] * 1e-3) / 1e9
     log(f"[bench] fp32 served: {solves32:.1f} solves/s, {eff32:.0f} GB/s effective; passes (ms) "
-        + ", ".join(f"{pass_names[p]}={avg_pass[p]:.4f}" for p in range(5)))
+        + ", ".join(f"{pass_names[p]}={avg_pass[p]:.4f}" for p in active))
 
     # accuracy of the FP32 served result (last step) against the GPU FP64 solve
     phi64 = plan64.solve(S64_dev)
@@ -315,16 +319,21 @@ def main():
         "copy_ceiling_GBps": round(copy_gbs, 1),
         "roofline_frac_effective": round(eff32 / HBM_PEAK_GBS, 4),
         "algorithmic_bytes_per_solve": bytes32,
+        "fused_xy_planes": plan32.fused,
+        "bytes_moved_per_solve": plan32.solve_bytes(),
+        "moved_GBps": round(plan32.solve_bytes() * solves32 / 1e9, 1),
         "step_ms_p50": round(percentile(step_ms, 50), 5),
         "step_ms_p99": round(percentile(step_ms, 99), 5),
-        "pass_ms_avg": {pass_names[p]: round(avg_pass[p], 5) for p in range(5)},
+        "pass_ms_avg": {pass_names[p]: round(avg_pass[p], 5) for p in active},
         "fp32_accuracy": acc32,
         "fp64_plain": {"solves_per_s": round(solves64, 2), "effective_GBps": round(eff64, 1),
                        "roofline_frac_effective": round(eff64 / HBM_PEAK_GBS, 4),
                        "latency_ms_p50": round(percentile(lat64, 50), 5),
                        "latency_ms_p99": round(percentile(lat64, 99), 5),
                        "solves_timed": R, "accuracy": acc64},
-        "roofline": {"bound": "hbm", "kernel": f"pass_kernel ({pass_names[dom]})",
+        "roofline": {"bound": "hbm",
+                     "kernel": f"{'plane_kernel' if pass_names[dom] in ('xy_fwd', 'yx_inv') else 'pass_kernel'} "
+                               f"({pass_names[dom]})",
                      "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                      "algorithmic_bytes_per_launch": dom_bytes,

@@ -74,7 +74,10 @@ typedef enum { PSPFFT_FP32 = 0, PSPFFT_FP64 = 1 } pspfft_precision;
 /* The five passes of one solve (Sec. 2.2.2: x transforms, transpose, y
  * transforms, transpose, z transforms with the multiply by the Green's-function
  * transform, then the reverse sequence).  On one GPU the transposes become
- * strided column passes over the workspace. */
+ * strided column passes over the workspace.  A fused plan (pspfft_plan_fused)
+ * does the x and y transforms of each z plane in one kernel: its
+ * PSPFFT_PASS_X_FWD also covers Y_FWD, its PSPFFT_PASS_X_INV also covers
+ * Y_INV, and its two y passes do nothing. */
 typedef enum {
     PSPFFT_PASS_X_FWD = 0,  /* zero-padded real-to-complex transforms along x     */
     PSPFFT_PASS_Y_FWD = 1,  /* transforms along y, upper half of the input zero   */
@@ -94,6 +97,29 @@ typedef enum {
 pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspfft_precision prec,
                                  pspfft_plan_t *out);
 
+/* Plan options for pspfft_plan_create_ex. */
+typedef enum {
+    PSPFFT_PLAN_DEFAULT = 0,
+    /* Always run the five separate passes, even where the x and y transforms
+     * of a plane could share one kernel. */
+    PSPFFT_PLAN_FIVE_PASS = 1
+} pspfft_plan_flags;
+
+/*
+ * As pspfft_plan_create, with options (a bitwise or of pspfft_plan_flags;
+ * unknown bits return PSPFFT_ERR_INVALID_ARGUMENT).  By default a plan fuses
+ * the x and y transforms of each z plane when nx == ny = E*K (E in
+ * {16, 20, 24, 36}, K a power of two dividing the power-of-two part of E, so at
+ * most two stages) and the plane of x spectra fits in the 160 KB of LDS: FP32
+ * up to n = 128, FP64 up to n = 80.  Both forms compute the same potential to
+ * rounding; the fused one moves 2ny nz (nx+1) fewer complex values per solve.
+ */
+pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], pspfft_precision prec,
+                                    unsigned flags, pspfft_plan_t *out);
+
+/* 1 if the plan runs fused x-y plane kernels, 0 otherwise (and for NULL). */
+int pspfft_plan_fused(pspfft_plan_t plan);
+
 /* Release a plan and everything it owns (Sec. 3.2, Destroy).  Synchronises the
  * device first.  NULL returns PSPFFT_ERR_INVALID_ARGUMENT. */
 pspfft_status pspfft_destroy(pspfft_plan_t plan);
@@ -103,7 +129,8 @@ pspfft_status pspfft_destroy(pspfft_plan_t plan);
  * reals in the plan's precision, layout as above.  S == Phi is allowed (the
  * paper overwrites the source with the potential).  Uses the plan's default
  * workspace, so solves on one plan serialise on that workspace: concurrent
- * solves need a workspace each (pspfft_solve_ws).  Enqueues five kernels.
+ * solves need a workspace each (pspfft_solve_ws).  Enqueues five kernels, or
+ * three for a fused plan.
  */
 pspfft_status pspfft_solve(pspfft_plan_t plan, const void *S, void *Phi, hipStream_t stream);
 
@@ -156,7 +183,8 @@ size_t pspfft_workspace_bytes(int nx, int ny, int nz, pspfft_precision prec);
 
 /* Algorithmic HBM bytes one pass moves for one problem of this plan: the
  * values it must read and write once each (zero halves never touched).  Used
- * for effective-bandwidth reports.  0 for NULL or an unknown pass. */
+ * for effective-bandwidth reports.  0 for NULL, an unknown pass, or a y pass of
+ * a fused plan (its x passes then count the fused traffic). */
 size_t pspfft_pass_bytes(pspfft_plan_t plan, pspfft_pass pass);
 
 /* Size, spacings and precision of a plan (any output pointer may be NULL). */

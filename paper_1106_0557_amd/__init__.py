@@ -42,10 +42,17 @@ def workspace_bytes(nx: int, ny: int, nz: int, dtype=torch.float32) -> int:
     return int(_lib.load().pspfft_workspace_bytes(nx, ny, nz, _prec(dtype)))
 
 
-class Plan:
-    """``pspfft_plan_create`` / ``pspfft_destroy`` (the paper's Create / Destroy)."""
+PLAN_FIVE_PASS = 1  # pspfft_plan_flags
 
-    def __init__(self, nx: int, ny: int, nz: int, h, dtype=torch.float32):
+
+class Plan:
+    """``pspfft_plan_create_ex`` / ``pspfft_destroy`` (the paper's Create / Destroy).
+
+    ``five_pass=True`` keeps the five separate passes where the x and y
+    transforms of a plane could otherwise share one kernel (``fused``).
+    """
+
+    def __init__(self, nx: int, ny: int, nz: int, h, dtype=torch.float32, five_pass: bool = False):
         lib = _lib.load()
         if isinstance(h, (int, float)):
             h = (float(h),) * 3
@@ -55,10 +62,15 @@ class Plan:
         self.dtype = dtype
         handle = ctypes.c_void_p()
         h3 = (ctypes.c_double * 3)(*self.h)
-        _lib.check(lib.pspfft_plan_create(int(nx), int(ny), int(nz), h3, _prec(dtype), ctypes.byref(handle)),
-                   f"pspfft_plan_create({nx},{ny},{nz})")
+        flags = PLAN_FIVE_PASS if five_pass else 0
+        _lib.check(lib.pspfft_plan_create_ex(int(nx), int(ny), int(nz), h3, _prec(dtype), flags,
+                                             ctypes.byref(handle)),
+                   f"pspfft_plan_create_ex({nx},{ny},{nz})")
         self._handle = handle.value
         self._lib = lib
+        self.fused = bool(lib.pspfft_plan_fused(self._handle))
+        # passes that launch work for this plan (a fused plan skips the y passes)
+        self.active_passes = tuple(p for p in range(5) if lib.pspfft_pass_bytes(self._handle, p) > 0)
 
     @property
     def handle(self) -> int:

@@ -116,19 +116,36 @@ __host__ __device__ constexpr int max_block_for(int prec, int E) {
     return prec == 0 ? (E == 16 ? 1024 : (E <= 24 ? 512 : 256)) : (E == 16 ? 512 : 256);
 }
 
+// Fused plane kernels (x and y transforms of one z plane per workgroup) for
+// nx == ny = n = E*K: n*K threads, the LDS plane (n rows of row_stride(n, K))
+// followed by the n - 1 stage twiddles, the n split factors and 2n values of
+// column 0.
+__host__ __device__ constexpr size_t plane_lds_bytes(int prec, int E, int K) {
+    const int n = E * K, csz = prec == 0 ? 8 : 16;
+    return static_cast<size_t>(n * row_stride(n, K, csz) + 4 * n - 1) * csz;
+}
+// FP64 workgroups stay at 256 threads or fewer, where the two line transforms
+// each thread holds fit in registers.
+__host__ __device__ constexpr bool plane_fits(int prec, int E, int K) {
+    return K >= 1 && K <= (E & -E) && E * K * K <= (prec == 0 ? 1024 : 256) &&
+           plane_lds_bytes(prec, E, K) <= 160 * 1024;
+}
+
 // Launchers: one per (precision, family), defined in pass_<prec>_e<E>.hip.
 // K is the radix of the last stage of the pass axis (1 for a single stage).
-#define PSPFFT_DECLARE_FAMILY(NAME)                                                                 \
+// The plane launchers run the forward (fwd) or inverse fused kernel with n*K threads.
+#define PSPFFT_DECLARE_FAMILY(NAME, PLANE)                                                          \
     hipError_t NAME(int mode, int K, bool fix, const LaunchArgs &args, int grid, int block,         \
-                    size_t lds, hipStream_t stream);
-PSPFFT_DECLARE_FAMILY(launch_f32_e16)
-PSPFFT_DECLARE_FAMILY(launch_f32_e20)
-PSPFFT_DECLARE_FAMILY(launch_f32_e24)
-PSPFFT_DECLARE_FAMILY(launch_f32_e36)
-PSPFFT_DECLARE_FAMILY(launch_f64_e16)
-PSPFFT_DECLARE_FAMILY(launch_f64_e20)
-PSPFFT_DECLARE_FAMILY(launch_f64_e24)
-PSPFFT_DECLARE_FAMILY(launch_f64_e36)
+                    size_t lds, hipStream_t stream);                                                \
+    hipError_t PLANE(bool fwd, int K, const LaunchArgs &args, int grid, size_t lds, hipStream_t stream);
+PSPFFT_DECLARE_FAMILY(launch_f32_e16, plane_f32_e16)
+PSPFFT_DECLARE_FAMILY(launch_f32_e20, plane_f32_e20)
+PSPFFT_DECLARE_FAMILY(launch_f32_e24, plane_f32_e24)
+PSPFFT_DECLARE_FAMILY(launch_f32_e36, plane_f32_e36)
+PSPFFT_DECLARE_FAMILY(launch_f64_e16, plane_f64_e16)
+PSPFFT_DECLARE_FAMILY(launch_f64_e20, plane_f64_e20)
+PSPFFT_DECLARE_FAMILY(launch_f64_e24, plane_f64_e24)
+PSPFFT_DECLARE_FAMILY(launch_f64_e36, plane_f64_e36)
 #undef PSPFFT_DECLARE_FAMILY
 
 inline hipError_t launch_pass(int mode, int prec, int E, int K, bool fix, const LaunchArgs &args, int grid,
@@ -143,6 +160,22 @@ inline hipError_t launch_pass(int mode, int prec, int E, int K, bool fix, const 
         case 120: return launch_f64_e20(mode, K, fix, args, grid, block, lds, stream);
         case 124: return launch_f64_e24(mode, K, fix, args, grid, block, lds, stream);
         case 136: return launch_f64_e36(mode, K, fix, args, grid, block, lds, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+inline hipError_t launch_plane(bool fwd, int prec, int E, int K, const LaunchArgs &args, int grid, size_t lds,
+                               hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
+    switch (prec * 100 + E) {
+        case 16: return plane_f32_e16(fwd, K, args, grid, lds, stream);
+        case 20: return plane_f32_e20(fwd, K, args, grid, lds, stream);
+        case 24: return plane_f32_e24(fwd, K, args, grid, lds, stream);
+        case 36: return plane_f32_e36(fwd, K, args, grid, lds, stream);
+        case 116: return plane_f64_e16(fwd, K, args, grid, lds, stream);
+        case 120: return plane_f64_e20(fwd, K, args, grid, lds, stream);
+        case 124: return plane_f64_e24(fwd, K, args, grid, lds, stream);
+        case 136: return plane_f64_e36(fwd, K, args, grid, lds, stream);
         default: return hipErrorInvalidValue;
     }
 }

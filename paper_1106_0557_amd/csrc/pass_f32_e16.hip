@@ -1,4 +1,4 @@
 // Pass kernels for float, radix family E = 16.
-#include "pass_kernels.h"
+#include "plane_kernels.h"
 
-PSPFFT_FAMILY(float, 16, launch_f32_e16)
+PSPFFT_FAMILY(float, 16, launch_f32_e16, plane_f32_e16)

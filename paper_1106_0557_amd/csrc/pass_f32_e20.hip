@@ -1,4 +1,4 @@
 // Pass kernels for float, radix family E = 20.
-#include "pass_kernels.h"
+#include "plane_kernels.h"
 
-PSPFFT_FAMILY(float, 20, launch_f32_e20)
+PSPFFT_FAMILY(float, 20, launch_f32_e20, plane_f32_e20)

@@ -1,4 +1,4 @@
 // Pass kernels for double, radix family E = 36.
-#include "pass_kernels.h"
+#include "plane_kernels.h"
 
-PSPFFT_FAMILY(double, 36, launch_f64_e36)
+PSPFFT_FAMILY(double, 36, launch_f64_e36, plane_f64_e36)

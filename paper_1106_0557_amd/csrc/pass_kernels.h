@@ -447,12 +447,3 @@ hipError_t launch_family(int mode, int K, bool fix, const LaunchArgs &args, int 
 }
 
 }  // namespace pspfft
-
-// One translation unit per (precision, family) keeps compiles parallel.
-#define PSPFFT_FAMILY(T, E, NAME)                                                                   \
-    namespace pspfft {                                                                              \
-    hipError_t NAME(int mode, int K, bool fix, const LaunchArgs &args, int grid, int block,         \
-                    size_t lds, hipStream_t stream) {                                               \
-        return launch_family<T, E>(mode, K, fix, args, grid, block, lds, stream);                   \
-    }                                                                                               \
-    }

@@ -36,6 +36,8 @@ struct pspfft_plan_s {
     pspfft_workspace_t ws = nullptr;  // default workspace
     size_t bytes = 0;
     int device = 0;
+    bool fused = false;      // x and y transforms of a z plane in one kernel
+    int pE = 0, pK = 0;      // radix family and last radix of those kernels
 };
 
 struct pspfft_workspace_s {
@@ -280,26 +282,15 @@ void pass_lines(int mode, const int n[3], long &main, long &nyq) {
     }
 }
 
-pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
-                       const void *const *S, void *const *Phi, hipStream_t stream) {
-    if (count < 0) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (count == 0) return PSPFFT_OK;
-    if (!plans || !ws) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (mode == pspfft::X_FWD && !S) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (mode == pspfft::X_INV && !Phi) return PSPFFT_ERR_INVALID_ARGUMENT;
-    for (int i = 0; i < count; ++i) {
-        if (!plans[i] || !ws[i] || ws[i]->plan != plans[i]) return PSPFFT_ERR_INVALID_ARGUMENT;
-        // the x passes move pairs of reals: S and Phi must be aligned to two reals
-        const uintptr_t al = 2 * real_size(plans[i]->prec);
-        if (mode == pspfft::X_FWD && (!S[i] || reinterpret_cast<uintptr_t>(S[i]) % al)) return PSPFFT_ERR_INVALID_ARGUMENT;
-        if (mode == pspfft::X_INV && (!Phi[i] || reinterpret_cast<uintptr_t>(Phi[i]) % al))
-            return PSPFFT_ERR_INVALID_ARGUMENT;
-    }
+// Grouped launches of a line pass (X_FWD .. X_INV kernels) for the problems idx.
+pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_plan_t *plans,
+                           const pspfft_workspace_t *ws, const void *const *S, void *const *Phi,
+                           hipStream_t stream) {
     const int axis = pspfft::pass_axis(mode);
     const bool row = axis == 0;
     // One kernel per (precision, radix family E, last-stage radix K) of the pass axis.
     std::map<std::tuple<int, int, int>, std::vector<int>> groups;
-    for (int i = 0; i < count; ++i) {
+    for (int i : all) {
         const AxisPlan &ax = plans[i]->host.ax[axis];
         const int K = ax.nst == 1 ? 1 : ax.R[ax.nst - 1];
         groups[{static_cast<int>(plans[i]->prec), ax.E, K}].push_back(i);
@@ -389,6 +380,86 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
     return PSPFFT_OK;
 }
 
+// Grouped launches of the fused plane kernels (forward or inverse) for the problems idx.
+pspfft_status launch_planes(bool fwd, const std::vector<int> &all, const pspfft_plan_t *plans,
+                            const pspfft_workspace_t *ws, const void *const *S, void *const *Phi,
+                            hipStream_t stream) {
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    for (int i : all) groups[{static_cast<int>(plans[i]->prec), plans[i]->pE, plans[i]->pK}].push_back(i);
+    for (auto &kv : groups) {
+        const int prec = std::get<0>(kv.first), E = std::get<1>(kv.first), K = std::get<2>(kv.first);
+        std::vector<int> idx = kv.second;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            return reinterpret_cast<uintptr_t>(plans[a]) < reinterpret_cast<uintptr_t>(plans[b]);
+        });
+        const size_t lds = pspfft::plane_lds_bytes(prec, E, K);
+        for (size_t c0 = 0; c0 < idx.size(); c0 += pspfft::kMaxProblems) {
+            const size_t c1 = std::min(idx.size(), c0 + pspfft::kMaxProblems);
+            LaunchArgs args;
+            std::memset(&args, 0, sizeof(args));
+            args.count = static_cast<int>(c1 - c0);
+            for (size_t j = c0; j < c1; ++j) {
+                const int i = idx[j];
+                ProbArg &a = args.p[j - c0];
+                a.plan = plans[i]->dev;
+                a.S = S ? S[i] : nullptr;
+                a.Phi = Phi ? Phi[i] : nullptr;
+                a.W = ws[i]->W;
+                a.Wn = ws[i]->Wn;
+                if (j > c0 && plans[idx[j - 1]] == plans[i]) {
+                    args.seg[args.nseg - 1].group += 1;
+                    continue;
+                }
+                pspfft::Segment &sg = args.seg[args.nseg++];
+                sg.first = static_cast<int>(j - c0);
+                sg.group = 1;
+            }
+            long wg = 0;
+            for (int k = 0; k < args.nseg; ++k) {  // one workgroup per z plane
+                pspfft::Segment &sg = args.seg[k];
+                const long nz = plans[idx[c0 + sg.first]]->n[2];
+                sg.wg_begin = static_cast<int>(wg);
+                sg.wg_main = static_cast<int>(nz);
+                wg += nz * sg.group;
+            }
+            args.nwg = static_cast<int>(wg);
+            PSPFFT_LOG(3, "plane %s prec %d E %d K %d: %d problems, %ld workgroups of %d threads, %zu B LDS",
+                       fwd ? "fwd" : "inv", prec, E, K, args.count, wg, E * K * K, lds);
+            if (pspfft::launch_plane(fwd, prec, E, K, args, static_cast<int>(wg), lds, stream) != hipSuccess)
+                return PSPFFT_ERR_DEVICE;
+        }
+    }
+    return PSPFFT_OK;
+}
+
+// One pass for `count` problems.  Plans with fused planes run their x and y
+// transforms together in X_FWD and X_INV and have nothing to do in Y_FWD and Y_INV.
+pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
+                       const void *const *S, void *const *Phi, hipStream_t stream) {
+    if (count < 0) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (count == 0) return PSPFFT_OK;
+    if (!plans || !ws) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (mode == pspfft::X_FWD && !S) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (mode == pspfft::X_INV && !Phi) return PSPFFT_ERR_INVALID_ARGUMENT;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !ws[i] || ws[i]->plan != plans[i]) return PSPFFT_ERR_INVALID_ARGUMENT;
+        // the x passes move pairs of reals: S and Phi must be aligned to two reals
+        const uintptr_t al = 2 * real_size(plans[i]->prec);
+        if (mode == pspfft::X_FWD && (!S[i] || reinterpret_cast<uintptr_t>(S[i]) % al)) return PSPFFT_ERR_INVALID_ARGUMENT;
+        if (mode == pspfft::X_INV && (!Phi[i] || reinterpret_cast<uintptr_t>(Phi[i]) % al))
+            return PSPFFT_ERR_INVALID_ARGUMENT;
+    }
+    std::vector<int> lines, planes;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i]->fused || mode == pspfft::Z_CONV) lines.push_back(i);
+        else if (mode == pspfft::X_FWD || mode == pspfft::X_INV) planes.push_back(i);
+    }
+    pspfft_status st = PSPFFT_OK;
+    if (!planes.empty()) st = launch_planes(mode == pspfft::X_FWD, planes, plans, ws, S, Phi, stream);
+    if (st == PSPFFT_OK && !lines.empty()) st = launch_lines(mode, lines, plans, ws, S, Phi, stream);
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -414,7 +485,13 @@ size_t pspfft_workspace_bytes(int nx, int ny, int nz, pspfft_precision prec) {
 
 pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspfft_precision prec,
                                  pspfft_plan_t *out) {
+    return pspfft_plan_create_ex(nx, ny, nz, h, prec, PSPFFT_PLAN_DEFAULT, out);
+}
+
+pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], pspfft_precision prec,
+                                    unsigned flags, pspfft_plan_t *out) {
     if (!out || !h) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (flags & ~static_cast<unsigned>(PSPFFT_PLAN_FIVE_PASS)) return PSPFFT_ERR_INVALID_ARGUMENT;
     if (prec != PSPFFT_FP32 && prec != PSPFFT_FP64) return PSPFFT_ERR_INVALID_ARGUMENT;
     for (int a = 0; a < 3; ++a)
         if (!(std::isfinite(h[a]) && h[a] > 0.0)) return PSPFFT_ERR_INVALID_ARGUMENT;
@@ -459,6 +536,17 @@ pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspf
         p->host.ax[a].tw = p->tw[a];
         p->host.ax[a].post = a == 0 ? static_cast<char *>(p->tw[a]) + p->host.ax[a].ntw * cs : nullptr;
         bytes += tb;
+    }
+    // fused x-y plane kernels: nx == ny = E*K (at most two stages) and the plane fits in LDS
+    {
+        const AxisPlan &ax = p->host.ax[0];
+        const int K = ax.nst == 1 ? 1 : ax.R[1];
+        p->fused = !(flags & PSPFFT_PLAN_FIVE_PASS) && nx == ny && ax.nst <= 2 && ax.E * K == nx &&
+                   ax.ntw == nx - 1 && pspfft::plane_fits(p->host.prec, ax.E, K);
+        if (p->fused) {
+            p->pE = ax.E;
+            p->pK = K;
+        }
     }
 
     // Green's-function spectrum, computed once in FP64 and kept (Sec. 2.2.2)
@@ -515,7 +603,8 @@ pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspf
     bytes += p->ws->bytes;
     p->bytes = bytes;
 
-    PSPFFT_LOG(2, "plan %dx%dx%d %s: %zu bytes resident", nx, ny, nz, prec == PSPFFT_FP32 ? "fp32" : "fp64", bytes);
+    PSPFFT_LOG(2, "plan %dx%dx%d %s: %zu bytes resident, %s", nx, ny, nz, prec == PSPFFT_FP32 ? "fp32" : "fp64",
+               bytes, p->fused ? "fused x-y planes" : "five passes");
     guard.armed = false;
     *out = p;
     return PSPFFT_OK;
@@ -610,6 +699,14 @@ size_t pspfft_pass_bytes(pspfft_plan_t plan, pspfft_pass pass) {
     const size_t nx = plan->n[0], ny = plan->n[1], nz = plan->n[2];
     const size_t half = ny * nz * (nx + 1) * c;  // spectrum rows y < ny (kx <= nx)
     const size_t full = 2 * half;                // all 2ny rows
+    if (plan->fused) {  // x and y transforms of a plane in one pass; no intermediate in HBM
+        switch (pass) {
+            case PSPFFT_PASS_X_FWD: return nx * ny * nz * r + full;
+            case PSPFFT_PASS_Z_CONV: return 2 * full + (nx + 1) * (ny + 1) * (nz + 1) * r;
+            case PSPFFT_PASS_X_INV: return full + nx * ny * nz * r;
+            default: return 0;
+        }
+    }
     switch (pass) {
         case PSPFFT_PASS_X_FWD: return nx * ny * nz * r + half;
         case PSPFFT_PASS_Y_FWD: return half + full;
@@ -619,6 +716,8 @@ size_t pspfft_pass_bytes(pspfft_plan_t plan, pspfft_pass pass) {
     }
     return 0;
 }
+
+int pspfft_plan_fused(pspfft_plan_t plan) { return plan && plan->fused ? 1 : 0; }
 
 pspfft_status pspfft_plan_info(pspfft_plan_t plan, int dims[3], double h[3], pspfft_precision *prec) {
     if (!plan) return PSPFFT_ERR_INVALID_ARGUMENT;

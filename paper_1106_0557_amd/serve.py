@@ -7,10 +7,11 @@ workspaces are pooled.  A request is admitted when its device footprint
 (workspace + output) fits the memory budget and an in-flight slot is free.
 
 Scheduling is at pass granularity.  Each scheduler step issues, for every
-in-flight request, the next of its five passes; requests at the same pass are
-grouped into one batched launch (``pspfft_pass_batched``), and the five pass
-groups of a step go to five streams so that different requests' work overlaps
-on the device.  A request admitted while others are in flight starts its first
+in-flight request, the next of its passes (five, or three for a plan that fuses
+the x and y transforms of each plane); requests at the same pass are grouped
+into one batched launch (``pspfft_pass_batched``), and the pass groups of a step
+go to separate streams so that different requests' work overlaps on the
+device.  A request admitted while others are in flight starts its first
 pass in the next step, so a solve never waits for a whole batch to finish.
 Steps are ordered by events: every stream of step k+1 waits for all of step k.
 Results do not depend on the mix: each problem is tiled the same way whatever
@@ -40,6 +41,7 @@ class Request:
     arrival: float = 0.0         # seconds, on the scheduler's clock
     phi: Any = None              # output, allocated at admission
     next_pass: int = -1          # -1 waiting, 0..4 next pass to issue, 5 all issued
+    passes: Tuple[int, ...] = tuple(range(NUM_PASSES))  # passes with work for this request's plan
     done: bool = False
     rejected: bool = False
     error: Optional[str] = None
@@ -87,6 +89,9 @@ class GpuExecutor:
     def workspace_bytes(self, req: Request) -> int:
         nx, ny, nz = req.n
         return self.ps.workspace_bytes(nx, ny, nz, self.dtype)
+
+    def active_passes(self, req: Request) -> Tuple[int, ...]:
+        return self.plan(req).active_passes
 
     def output_bytes(self, req: Request) -> int:
         nx, ny, nz = req.n
@@ -222,7 +227,9 @@ class Server:
             req.phi = self.ex.alloc_output(req)
             self.used += need
             self.max_used = max(self.max_used, self.used)
-            req.next_pass = 0
+            active = getattr(self.ex, "active_passes", None)
+            req.passes = tuple(active(req)) if active else tuple(range(NUM_PASSES))
+            req.next_pass = req.passes[0]
             req.t_admit = self.now()
             self.inflight.append(req)
 
@@ -264,7 +271,8 @@ class Server:
         completing = []
         still = []
         for r in self.inflight:
-            r.next_pass += 1
+            later = [p for p in r.passes if p > r.next_pass]
+            r.next_pass = later[0] if later else NUM_PASSES
             (completing if r.next_pass == NUM_PASSES else still).append(r)
         self.inflight = still
         self.steps.append((token, completing))

@@ -105,6 +105,17 @@ def test_plan_create_rejects_bad_arguments_before_device_work(lib):
     assert lib.pspfft_plan_create(16, 16, 16, h3, 0, None) == 1
 
 
+def test_plan_create_ex_rejects_unknown_flags_before_device_work(lib):
+    h3 = (ctypes.c_double * 3)(1, 1, 1)
+    handle = ctypes.c_void_p()
+    for flags in (2, 4, 0x80000000, 3):
+        assert lib.pspfft_plan_create_ex(16, 16, 16, h3, 0, flags, ctypes.byref(handle)) == 1
+        assert handle.value is None
+    assert lib.pspfft_plan_create_ex(16, 16, 16, h3, 0, 0, None) == 1
+    assert lib.pspfft_plan_create_ex(16, 16, 16, None, 0, 1, ctypes.byref(handle)) == 1
+    assert lib.pspfft_plan_create_ex(16, 16, 15, h3, 0, 1, ctypes.byref(handle)) == 2
+
+
 def test_null_handles(lib):
     assert lib.pspfft_destroy(None) == 1
     assert lib.pspfft_workspace_destroy(None) == 1
@@ -114,6 +125,7 @@ def test_null_handles(lib):
     assert lib.pspfft_pass_bytes(None, 0) == 0
     assert lib.pspfft_plan_info(None, None, None, None) == 1
     assert lib.pspfft_plan_green(None, None, None) == 1
+    assert lib.pspfft_plan_fused(None) == 0
     # an empty batch is a no-op; a negative count is an error
     assert lib.pspfft_solve_batched(0, None, None, None, None, None) == 0
     assert lib.pspfft_solve_batched(-1, None, None, None, None, None) == 1
