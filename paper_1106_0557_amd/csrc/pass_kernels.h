@@ -156,8 +156,41 @@ __device__ __forceinline__ void copy_to_lds(cx<T> *dst, const void *src, int cou
     for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = s[i];
 }
 
-// FIX: every problem of the launch has a two-stage line (L = E*K, NB = K) and the
-// workgroup holds the default number of lines, so the geometry is compile-time.
+// Global-address-space view of a pointer that came from device memory (the
+// compiler cannot infer it), so its loads are global rather than flat ones.
+template <typename U>
+using gbl = __attribute__((address_space(1))) U;
+template <typename U>
+__device__ __forceinline__ const gbl<U> *as_global(const U *p) {
+    return (const gbl<U> *)p;
+}
+
+// Element m of a line: base + lane + m*step bytes.  OFF32 (set by the host when
+// every array of the launch is below 2 GB): the offset lane + m*step is
+// computed in 32 bits and added to the workgroup-uniform base, so each access
+// is a scalar base plus one 32-bit vector offset.
+template <typename T, bool OFF32>
+struct LinePtr {
+    char *base;
+    size_t lane;
+    size_t step;
+    __device__ __forceinline__ cx<T> &operator[](int m) const {
+        if constexpr (OFF32)
+            return *reinterpret_cast<cx<T> *>(
+                base + (static_cast<uint32_t>(lane) + static_cast<uint32_t>(m) * static_cast<uint32_t>(step)));
+        else
+            return *reinterpret_cast<cx<T> *>(base + lane + static_cast<size_t>(m) * step);
+    }
+};
+template <typename T, bool OFF32>
+__device__ __forceinline__ LinePtr<T, OFF32> line_ptr(const void *base, size_t lane_elems, size_t step_elems,
+                                                      size_t esz) {
+    return LinePtr<T, OFF32>{const_cast<char *>(static_cast<const char *>(base)), lane_elems * esz, step_elems * esz};
+}
+
+// FIX: every problem of the launch has a two-stage line (L = E*K, NB = K), the
+// workgroup holds the default number of lines, so the geometry is compile-time,
+// and every array is below 2 GB, so addresses use 32-bit lane offsets.
 template <typename T, int E, int K, int MODE, bool FIX>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pass_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -230,14 +263,16 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         const bool active = g < nrows;
         const int z = active ? g / ny : 0;
         const int y = g - z * ny;
-        cx<T> *wrow = W + (static_cast<size_t>(z) * 2 * ny + y) * nx;
+        const size_t wrow = (static_cast<size_t>(z) * 2 * ny + y) * nx;  // row start in W (elements)
         cx<T> *wnyq = Wn + static_cast<size_t>(z) * 2 * ny + y;
+        // thread t's positions t + NB*m of row g of S / Phi (pairs of reals) and of W
+        const auto fld = line_ptr<T, FIX>(MODE == X_FWD ? pa.S : pa.Phi,
+                                          static_cast<size_t>(active ? g : 0) * nx / 2 + t, NB, CSZ);
+        const auto wl = line_ptr<T, FIX>(W, wrow + t, NB, CSZ);
         if constexpr (MODE == X_FWD) {
-            const cx<T> *srow =
-                reinterpret_cast<const cx<T> *>(static_cast<const T *>(pa.S) + static_cast<size_t>(g) * nx) + t;
 #pragma unroll
             for (int m = 0; m < E; ++m) {
-                if (m < H && active) v[m] = srow[NB * m];
+                if (m < H && active) v[m] = fld[m];
                 else v[m] = cx<T>{T(0), T(0)};
             }
             FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
@@ -263,7 +298,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                     const cx<T> a = {static_cast<T>(0.5) * (u.x + w.x), static_cast<T>(0.5) * (u.y - w.y)};
                     const cx<T> b = {static_cast<T>(0.5) * (u.x - w.x), static_cast<T>(0.5) * (u.y + w.y)};
                     const cx<T> eb = cmul(post[k], b);
-                    wrow[k] = cx<T>{a.x + eb.y, a.y - eb.x};  // a - i e b
+                    wl[m] = cx<T>{a.x + eb.y, a.y - eb.x};  // a - i e b
                     if (k == 0) *wnyq = cx<T>{u.x - u.y, T(0)};
                 }
             }
@@ -272,7 +307,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             // Each thread loads its own X[k]; the partners come through LDS.
 #pragma unroll
             for (int m = 0; m < E; ++m) {
-                if (active) v[m] = wrow[t + NB * m];
+                if (active) v[m] = wl[m];
                 else v[m] = cx<T>{T(0), T(0)};
             }
             cx<T> xn = {T(0), T(0)};
@@ -302,16 +337,14 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             }
             FFT_I::template run<K>(v, ax, lds, ldsw, twl, c, t);
             if (active) {
-                cx<T> *prow =
-                    reinterpret_cast<cx<T> *>(static_cast<T *>(pa.Phi) + static_cast<size_t>(g) * nx) + t;
 #pragma unroll
-                for (int m = 0; m < H; ++m) prow[NB * m] = v[m];
+                for (int m = 0; m < H; ++m) fld[m] = v[m];
             }
         }
     } else {
-        // Column passes: line g starts at `base`, elements `es` apart.
-        cx<T> *base;
-        size_t es;
+        // Column passes: line g starts at element `base` of `arr`, elements `es` apart.
+        const cx<T> *arr;
+        size_t base, es;
         bool active;
         int ky = 0, kx = 0;
         if constexpr (MODE == Z_CONV) {
@@ -323,13 +356,15 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 const int vrow = active ? g / nx : 0;
                 kx = g - vrow * nx;
                 ky = vrow == 0 ? 0 : (vrow == 2 * ny - 1 ? ny : ((vrow & 1) ? (vrow + 1) >> 1 : 2 * ny - (vrow >> 1)));
-                base = W + static_cast<size_t>(ky) * nx + kx;
+                arr = W;
+                base = static_cast<size_t>(ky) * nx + kx;
                 es = static_cast<size_t>(2) * ny * nx;
             } else {
                 active = g < 2 * ny;
                 ky = g;
                 kx = nx;
-                base = Wn + g;
+                arr = Wn;
+                base = static_cast<size_t>(g);
                 es = static_cast<size_t>(2) * ny;
             }
         } else {
@@ -337,24 +372,25 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 active = g < nz * nx;
                 const int z = active ? g / nx : 0;
                 kx = g - z * nx;
-                base = W + static_cast<size_t>(z) * 2 * ny * nx + kx;
+                arr = W;
+                base = static_cast<size_t>(z) * 2 * ny * nx + kx;
                 es = nx;
             } else {
                 active = g < nz;
-                base = Wn + static_cast<size_t>(g) * 2 * ny;
+                arr = Wn;
+                base = static_cast<size_t>(active ? g : 0) * 2 * ny;
                 es = 1;
             }
         }
-        cx<T> *lane = base + t * es;  // this thread's position t; position t + NB*m is m*step further
-        const size_t step = static_cast<size_t>(NB) * es;
+        // this thread's position t; position t + NB*m is m*NB*es elements further.
+        // An inactive line (past the end of a partial tile) reads in-bounds
+        // dummies from the start of the array and stores nothing.
+        const auto lane = line_ptr<T, FIX>(arr, active ? base + t * es : 0, static_cast<size_t>(NB) * es, CSZ);
         // Forward transforms read only the stored half (m < H); inverse ones
         // read the whole line.
         constexpr int nload = (MODE == Y_INV) ? E : H;
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            if (m < nload && active) v[m] = lane[m * step];
-            else v[m] = cx<T>{T(0), T(0)};
-        }
+        for (int m = 0; m < E; ++m) v[m] = m < nload ? lane[m] : cx<T>{T(0), T(0)};
         if constexpr (MODE == Y_FWD) {
             FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
         } else if constexpr (MODE == Y_INV) {
@@ -365,17 +401,26 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             // index min(k, 2n - k); for position P = t + NB*m that is t + NB*m when
             // m < H and NB*(E - m) - t otherwise.
             const int kyo = ky <= ny ? ky : 2 * ny - ky;
-            const T *Gp = nyq ? static_cast<const T *>(pl.Gn) + kyo
-                              : static_cast<const T *>(pl.G) + static_cast<size_t>(kyo) * nx + kx;
+            const void *Garr = nyq ? pl.Gn : pl.G;
+            const size_t gb = nyq ? static_cast<size_t>(kyo) : static_cast<size_t>(kyo) * nx + kx;
             const size_t gs = nyq ? static_cast<size_t>(ny + 1) : static_cast<size_t>(ny + 1) * nx;
-            const T *glo = Gp + t * gs;
-            const T *ghi = Gp - t * gs;
-            const size_t gstep = static_cast<size_t>(NB) * gs;
+            const size_t RS = sizeof(T);
+            // positions t + NB*m (m < H) from glane, NB*(E - m) - t (m >= H) from
+            // ghane; an inactive line reads in-bounds dummies from offset 0
+            const gbl<const char> *gbase = as_global(static_cast<const char *>(Garr));
+            const size_t glane = active ? (gb + t * gs) * RS : 0, ghane = active ? (gb + (NB - t) * gs) * RS : 0;
+            const size_t gstep = static_cast<size_t>(NB) * gs * RS;
             T gv[E];
 #pragma unroll
             for (int m = 0; m < E; ++m) {
-                if (active) gv[m] = m < H ? glo[m * gstep] : ghi[(E - m) * gstep];
-                else gv[m] = T(0);
+                const size_t idx = m < H ? m : E - m - 1;
+                if constexpr (FIX) {
+                    const uint32_t o = static_cast<uint32_t>(m < H ? glane : ghane) +
+                                       static_cast<uint32_t>(idx) * static_cast<uint32_t>(gstep);
+                    gv[m] = *reinterpret_cast<const gbl<T> *>(gbase + o);
+                } else {
+                    gv[m] = *reinterpret_cast<const gbl<T> *>(gbase + (m < H ? glane : ghane) + idx * gstep);
+                }
             }
             FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
 #pragma unroll
@@ -386,7 +431,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         constexpr int nstore = (MODE == Y_FWD) ? E : H;
         if (active) {
 #pragma unroll
-            for (int m = 0; m < nstore; ++m) lane[m * step] = v[m];
+            for (int m = 0; m < nstore; ++m) lane[m] = v[m];
         }
     }
 }

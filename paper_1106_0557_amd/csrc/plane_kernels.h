@@ -24,15 +24,55 @@
 // workgroup; the geometry is compile-time.
 #pragma once
 
+#include <cstdlib>
+
 #include "pass_kernels.h"
 
 namespace pspfft {
 
+// Keep a lane offset opaque to loop-invariant code motion, so that the
+// per-element offsets derived from it are recomputed inside the plane loop
+// (one add each) instead of being hoisted out and held in registers.
+template <typename I>
+__device__ __forceinline__ void opaque(I &v) { asm volatile("" : "+v"(v)); }
+
+// Element at byte offset `off` (32 bits) from a base pointer that is the same
+// for the whole workgroup, so the address is a scalar base plus one 32-bit
+// vector offset instead of a 64-bit vector address per element.
+template <typename T>
+__device__ __forceinline__ const cx<T> &at(const void *base, uint32_t off) {
+    return *reinterpret_cast<const cx<T> *>(static_cast<const char *>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> &at(void *base, uint32_t off) {
+    return *reinterpret_cast<cx<T> *>(static_cast<char *>(base) + off);
+}
+
+// Problem and z of plane `pl` of a launch (segments are numbered plane-major
+// within a run of problems that share a plan).
+struct PlaneRef {
+    const ProbArg *pa;
+    int z;
+};
+__device__ __forceinline__ PlaneRef plane_ref(const LaunchArgs &args, int pl) {
+    int sgi = 0;
+    while (sgi + 1 < args.nseg && pl >= args.seg[sgi + 1].wg_begin) ++sgi;
+    const Segment &sg = args.seg[sgi];
+    const int local = pl - sg.wg_begin;
+    return PlaneRef{&args.p[sg.first + local % sg.group], local / sg.group};
+}
+
+// Each workgroup takes planes blockIdx.x, blockIdx.x + gridDim.x, ...  The
+// forward kernel's stores of one plane drain while it works on the next.  The
+// inverse kernel loads the odd W rows of a plane while it transforms the even
+// ones, and the next plane's even rows (and Nyquist column) during the x step;
+// a whole plane of input would not fit in registers beside the one in use.
 template <typename T, int E, int K, bool FWD>
 __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args) {
     constexpr int n = E * K;
     constexpr int NB = K;
     constexpr int H = E / 2;
+    constexpr int BLK = E * K * K;  // threads: n lines of NB threads
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
     constexpr int SP = row_stride(n, NB, CSZ);  // LDS row stride of the plane
     using RowF = LineFFT<T, E, -1, true, NB, SP>;
@@ -43,181 +83,272 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
 
-    const int bid = static_cast<int>(blockIdx.x);
-    if (bid >= args.nwg) return;
-    int sgi = 0;
-    while (sgi + 1 < args.nseg && bid >= args.seg[sgi + 1].wg_begin) ++sgi;
-    const Segment &sg = args.seg[sgi];
-    const int local = bid - sg.wg_begin;
-    const int member = local % sg.group;
-    const int z = local / sg.group;
-    const ProbArg &pa = args.p[sg.first + member];
-    const AxisPlan &ax = pa.plan->ax[0];
+    const int G = static_cast<int>(gridDim.x);
+    int pl = static_cast<int>(blockIdx.x);
+    if (pl >= args.nwg) return;
 
-    // stage twiddles (n - 1 entries), exp(-i pi k / n) (k < n), and 2n slots
-    // for column 0 of the forward y step
+    // stage twiddles (n - 1 entries), exp(-i pi k / n) (k < n), and 2n slots for
+    // column 0 (forward) or the Nyquist column (inverse).  The tables depend on
+    // n only, so every problem of the launch shares them.
+    const AxisPlan &ax = args.p[0].plan->ax[0];
     cx<T> *twl = lds + n * SP;
     const cx<T> *post = twl + (n - 1);
     cx<T> *sep = twl + (2 * n - 1);
     copy_to_lds<T>(twl, ax.tw, 2 * n - 1);
 
-    const int tid = static_cast<int>(threadIdx.x);
-    cx<T> *Wz = static_cast<cx<T> *>(pa.W) + static_cast<size_t>(z) * 2 * n * n;
-    cx<T> *Wnz = static_cast<cx<T> *>(pa.Wn) + static_cast<size_t>(z) * 2 * n;
+    int tid = static_cast<int>(threadIdx.x);
+    // x step: row y = xc, thread xt of the row; y step: column kx = yc, thread yt
+    // of the column, at position cp within an LDS row.  Recomputed per plane
+    // from an opaque tid (see opaque()).
+    int xc, xt, yc, yt, cp;
+    auto lanes = [&]() {
+        opaque(tid);
+        xc = tid / NB;
+        xt = tid % NB;
+        yc = tid % n;
+        yt = tid / n;
+        cp = yc + (yc >> 4);
+    };
+    lanes();
+
+    auto W_of = [&](const PlaneRef &r) {
+        return static_cast<cx<T> *>(r.pa->W) + static_cast<size_t>(r.z) * 2 * n * n;
+    };
+    auto Wn_of = [&](const PlaneRef &r) { return static_cast<cx<T> *>(r.pa->Wn) + static_cast<size_t>(r.z) * 2 * n; };
 
     if constexpr (FWD) {
-        {  // x step: row c = y, thread t of the row
-            const int c = tid / NB, t = tid % NB;
-            cx<T> v[E];
-            const cx<T> *src =
-                reinterpret_cast<const cx<T> *>(static_cast<const T *>(pa.S) + (static_cast<size_t>(z) * n + c) * n) + t;
+        cx<T> s[H];  // this thread's packed source values of the current plane
+        auto load_src = [&](int p) {
+            const PlaneRef r = plane_ref(args, p);
+            const uint32_t src_off = static_cast<uint32_t>((xc * n + 2 * xt) * sizeof(T));
+            const void *plane = static_cast<const T *>(r.pa->S) + static_cast<size_t>(r.z) * n * n;
 #pragma unroll
-            for (int m = 0; m < E; ++m) v[m] = m < H ? src[NB * m] : cx<T>{T(0), T(0)};
-            RowF::template run<K>(v, ax, lds, SP, twl, c, t);
-            // U[k] to the row (each thread writes the positions its last gather read)
-            cx<T> *row = lds + c * SP;
+            for (int m = 0; m < H; ++m) s[m] = at<T>(plane, src_off + m * NB * CSZ);
+        };
+        for (;;) {
+            lanes();
+            load_src(pl);
+            const uint32_t wy_off = static_cast<uint32_t>((2 * yt * n + yc) * CSZ);  // W row 2*yt, column yc
+            const PlaneRef r = plane_ref(args, pl);
+            cx<T> *Wz = W_of(r);
+            cx<T> *Wnz = Wn_of(r);
+            {  // x step
+                cx<T> v[E];
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int P = t + NB * m;
-                row[P + (P >> 4)] = v[m];
-            }
-            __syncthreads();
-            // X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k])
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int k = t + NB * m;
-                const int kp = k == 0 ? 0 : n - k;
-                const cx<T> u = v[m];
-                const cx<T> w = row[kp + (kp >> 4)];
-                const cx<T> a = {static_cast<T>(0.5) * (u.x + w.x), static_cast<T>(0.5) * (u.y - w.y)};
-                const cx<T> b = {static_cast<T>(0.5) * (u.x - w.x), static_cast<T>(0.5) * (u.y + w.y)};
-                const cx<T> eb = cmul(post[k], b);
-                v[m] = cx<T>{a.x + eb.y, a.y - eb.x};
-                if (m == 0 && t == 0) v[m].y = u.x - u.y;  // X[0] is real: its imaginary slot takes X[n]
-            }
-            __syncthreads();  // partner reads done
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int P = t + NB * m;
-                row[P + (P >> 4)] = v[m];
-            }
-        }
-        __syncthreads();
-        {  // y step: column c = kx, thread t of the column
-            const int c = tid % n, t = tid / n;
-            const int cp = c + (c >> 4);
-            cx<T> v[E], w[E];
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int y = t + NB * m;
-                v[m] = lds[y * SP + cp];
-                w[m] = cmul(v[m], post[y]);
-            }
-            // Column 0 parks its values in `sep`; the other columns go straight to W.
-            auto emit = [&](const cx<T> *r, const int parity) {
-                if (c == 0) {
-#pragma unroll
-                    for (int m = 0; m < E; ++m) sep[2 * (t + NB * m) + parity] = r[m];
-                } else {
-#pragma unroll
-                    for (int m = 0; m < E; ++m) {
-                        const int ky = 2 * (t + NB * m) + parity;
-                        Wz[static_cast<size_t>(ky) * n + c] = r[m];
-                    }
-                }
-            };
-            ColF::template run<K>(v, ax, lds, SP, twl, cp, t);  // Y[2j]
-            emit(v, 0);
-            ColF::template run<K>(w, ax, lds, SP, twl, cp, t);  // Y[2j+1]
-            emit(w, 1);
-        }
-        __syncthreads();
-        // The first wave separates column 0: C = A + i B with A, B the transforms
-        // of the real columns kx = 0 and kx = n.
-        constexpr int NT = E * K * K < 64 ? E * K * K : 64;
-        if (tid < NT) {
-            for (int ky = tid; ky < 2 * n; ky += NT) {
-                const int kp = ky == 0 ? 0 : 2 * n - ky;
-                const cx<T> C = sep[ky];
-                const cx<T> Cp = sep[kp];
-                Wz[static_cast<size_t>(ky) * n] =
-                    cx<T>{static_cast<T>(0.5) * (C.x + Cp.x), static_cast<T>(0.5) * (C.y - Cp.y)};
-                Wnz[ky] = cx<T>{static_cast<T>(0.5) * (C.y + Cp.y), static_cast<T>(-0.5) * (C.x - Cp.x)};
-            }
-        }
-    } else {
-        {  // y step: column c = kx (kx = 0 also carries kx = n), thread t
-            const int c = tid % n, t = tid / n;
-            const int cp = c + (c >> 4);
-            cx<T> v[E], w[E];
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int j = t + NB * m;
-                v[m] = Wz[static_cast<size_t>(2 * j) * n + c];
-                w[m] = Wz[static_cast<size_t>(2 * j + 1) * n + c];
-            }
-            if (c == 0) {
+                for (int m = 0; m < E; ++m) v[m] = m < H ? s[m] : cx<T>{T(0), T(0)};
+                RowF::template run<K>(v, ax, lds, SP, twl, xc, xt);
+                // U[k] to the row (each thread writes the positions its last gather read)
+                cx<T> *row = lds + xc * SP;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
-                    const int j = t + NB * m;
-                    const cx<T> a = Wnz[2 * j], b = Wnz[2 * j + 1];
-                    v[m] = cx<T>{v[m].x - a.y, v[m].y + a.x};
-                    w[m] = cx<T>{w[m].x - b.y, w[m].y + b.x};
+                    const int P = xt + NB * m;
+                    row[P + (P >> 4)] = v[m];
+                }
+                __syncthreads();
+                // X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k])
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int k = xt + NB * m;
+                    const int kp = k == 0 ? 0 : n - k;
+                    const cx<T> u = v[m];
+                    const cx<T> w = row[kp + (kp >> 4)];
+                    const cx<T> a = {static_cast<T>(0.5) * (u.x + w.x), static_cast<T>(0.5) * (u.y - w.y)};
+                    const cx<T> b = {static_cast<T>(0.5) * (u.x - w.x), static_cast<T>(0.5) * (u.y + w.y)};
+                    const cx<T> eb = cmul(post[k], b);
+                    v[m] = cx<T>{a.x + eb.y, a.y - eb.x};
+                    if (m == 0 && xt == 0) v[m].y = u.x - u.y;  // X[0] is real: its imaginary slot takes X[n]
+                }
+                __syncthreads();  // partner reads done
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int P = xt + NB * m;
+                    row[P + (P >> 4)] = v[m];
                 }
             }
-            ColI::template run<K>(v, ax, lds, SP, twl, cp, t);
-            ColI::template run<K>(w, ax, lds, SP, twl, cp, t);
-            if constexpr (K == 1) __syncthreads();  // post table visible
-            // x[y] = A[y] + e^{+i pi y/n} B[y]; each thread writes the positions its last gather read
+            __syncthreads();
+            const int nxt = pl + G;
+            {  // y step
+                cx<T> v[E], w[E];
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int y = t + NB * m;
-                lds[y * SP + cp] = v[m] + cmulc(w[m], post[y]);
+                for (int m = 0; m < E; ++m) {
+                    const int y = yt + NB * m;
+                    v[m] = lds[y * SP + cp];
+                    w[m] = cmul(v[m], post[y]);
+                }
+                // Column 0 parks its values in `sep`; the other columns go straight to W.
+                auto emit = [&](const cx<T> *q, const int parity) {
+                    if (yc == 0) {
+#pragma unroll
+                        for (int m = 0; m < E; ++m) sep[2 * (yt + NB * m) + parity] = q[m];
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < E; ++m) at<T>(Wz, wy_off + (m * 2 * NB + parity) * n * CSZ) = q[m];
+                    }
+                };
+                ColF::template run<K>(v, ax, lds, SP, twl, cp, yt);  // Y[2j]
+                emit(v, 0);
+                ColF::template run<K>(w, ax, lds, SP, twl, cp, yt);  // Y[2j+1]
+                emit(w, 1);
             }
+            __syncthreads();
+            // The first wave separates column 0: C = A + i B with A, B the transforms
+            // of the real columns kx = 0 and kx = n.
+            constexpr int NT = BLK < 64 ? BLK : 64;
+            if (tid < NT) {
+                for (int ky = tid; ky < 2 * n; ky += NT) {
+                    const int kp = ky == 0 ? 0 : 2 * n - ky;
+                    const cx<T> C = sep[ky];
+                    const cx<T> Cp = sep[kp];
+                    Wz[static_cast<size_t>(ky) * n] =
+                        cx<T>{static_cast<T>(0.5) * (C.x + Cp.x), static_cast<T>(0.5) * (C.y - Cp.y)};
+                    Wnz[ky] = cx<T>{static_cast<T>(0.5) * (C.y + Cp.y), static_cast<T>(-0.5) * (C.x - Cp.x)};
+                }
+            }
+            if (nxt >= args.nwg) break;
+            pl = nxt;
+            __syncthreads();  // LDS readers of this plane are done
         }
-        __syncthreads();
-        {  // x step: row c = y, thread t
-            const int c = tid / NB, t = tid % NB;
-            const cx<T> *row = lds + c * SP;
-            const cx<T> p0 = row[0];  // X[y][0] + i X[y][n], both real
-            cx<T> v[E];
-            // U[k] = (X[k] + X*[n-k]) + i exp(+i pi k/n) (X[k] - X*[n-k])
+    } else {
+        constexpr int NWV = (2 * n + BLK - 1) / BLK;  // Nyquist values per thread
+        cx<T> e[E];     // even W rows of this thread's column, current plane
+        cx<T> nw[NWV];  // Nyquist column of the next plane, on its way to `sep`
+        // The Nyquist values are loaded first, so that waiting for them leaves the
+        // even rows in flight.
+        auto load_even = [&](int p) {
+            const PlaneRef r = plane_ref(args, p);
+            const cx<T> *Wz = W_of(r);
+            const cx<T> *Wnz = Wn_of(r);
+            const uint32_t even_off = static_cast<uint32_t>((2 * yt * n + yc) * CSZ);
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int k = t + NB * m;
-                cx<T> a, b;
-                if (m == 0 && t == 0) {
-                    a = cx<T>{p0.x, T(0)};
-                    b = cx<T>{p0.y, T(0)};
-                } else {
-                    const int kp = n - k;
-                    a = row[k + (k >> 4)];
-                    b = row[kp + (kp >> 4)];
-                }
-                const cx<T> sm = {a.x + b.x, a.y - b.y};
-                const cx<T> df = {a.x - b.x, a.y + b.y};
-                const cx<T> ed = cmulc(df, post[k]);
-                v[m] = cx<T>{sm.x - ed.y, sm.y + ed.x};
+            for (int q = 0; q < NWV; ++q) {  // clamped, so every thread loads (no divergent definition)
+                const int i = tid + q * BLK;
+                nw[q] = Wnz[i < 2 * n ? i : 2 * n - 1];
             }
-            RowI::template run<K>(v, ax, lds, SP, twl, c, t);
-            cx<T> *dst =
-                reinterpret_cast<cx<T> *>(static_cast<T *>(pa.Phi) + (static_cast<size_t>(z) * n + c) * n) + t;
 #pragma unroll
-            for (int m = 0; m < H; ++m) dst[NB * m] = v[m];
+            for (int m = 0; m < E; ++m) e[m] = at<T>(Wz, even_off + m * 2 * NB * n * CSZ);
+        };
+        auto stage_nyquist = [&]() {
+#pragma unroll
+            for (int q = 0; q < NWV; ++q) {
+                const int i = tid + q * BLK;
+                if (i < 2 * n) sep[i] = nw[q];
+            }
+        };
+        load_even(pl);
+        stage_nyquist();
+        for (;;) {
+            lanes();
+            const uint32_t even_off = static_cast<uint32_t>((2 * yt * n + yc) * CSZ);
+            const PlaneRef r = plane_ref(args, pl);
+            const cx<T> *Wz = W_of(r);
+            cx<T> o[E];  // odd rows, in flight while the even ones are transformed
+#pragma unroll
+            for (int m = 0; m < E; ++m) o[m] = at<T>(Wz, even_off + (m * 2 * NB + 1) * n * CSZ);
+            __syncthreads();  // Nyquist column and twiddles visible
+            {  // y step: column kx = 0 also carries kx = n (as Y0 + i Yn)
+                if (yc == 0) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const cx<T> a = sep[2 * (yt + NB * m)];
+                        e[m] = cx<T>{e[m].x - a.y, e[m].y + a.x};
+                    }
+                }
+                ColI::template run<K>(e, ax, lds, SP, twl, cp, yt);
+                if (yc == 0) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const cx<T> b = sep[2 * (yt + NB * m) + 1];
+                        o[m] = cx<T>{o[m].x - b.y, o[m].y + b.x};
+                    }
+                }
+                ColI::template run<K>(o, ax, lds, SP, twl, cp, yt);
+                // x[y] = A[y] + e^{+i pi y/n} B[y]; each thread writes the positions its last gather read
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int y = yt + NB * m;
+                    lds[y * SP + cp] = e[m] + cmulc(o[m], post[y]);
+                }
+            }
+            __syncthreads();
+            const int nxt = pl + G;
+            if (nxt < args.nwg) load_even(nxt);
+            {  // x step
+                const cx<T> *row = lds + xc * SP;
+                const cx<T> p0 = row[0];  // X[y][0] + i X[y][n], both real
+                cx<T> v[E];
+                // U[k] = (X[k] + X*[n-k]) + i exp(+i pi k/n) (X[k] - X*[n-k])
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int k = xt + NB * m;
+                    cx<T> a, b;
+                    if (m == 0 && xt == 0) {
+                        a = cx<T>{p0.x, T(0)};
+                        b = cx<T>{p0.y, T(0)};
+                    } else {
+                        const int kp = n - k;
+                        a = row[k + (k >> 4)];
+                        b = row[kp + (kp >> 4)];
+                    }
+                    const cx<T> sm = {a.x + b.x, a.y - b.y};
+                    const cx<T> df = {a.x - b.x, a.y + b.y};
+                    const cx<T> ed = cmulc(df, post[k]);
+                    v[m] = cx<T>{sm.x - ed.y, sm.y + ed.x};
+                }
+                RowI::template run<K>(v, ax, lds, SP, twl, xc, xt);
+                void *plane = static_cast<T *>(r.pa->Phi) + static_cast<size_t>(r.z) * n * n;
+                const uint32_t off = static_cast<uint32_t>((xc * n + 2 * xt) * sizeof(T));
+#pragma unroll
+                for (int m = 0; m < H; ++m) at<T>(plane, off + m * NB * CSZ) = v[m];
+            }
+            if (nxt < args.nwg) stage_nyquist();  // `sep` is free until the next y step
+            if (nxt >= args.nwg) break;
+            pl = nxt;
+            __syncthreads();  // LDS readers of this plane are done
         }
     }
 }
 
-template <typename T, int E, int K, bool FWD>
-hipError_t launch_plane_kernel(const LaunchArgs &args, int grid, size_t lds, hipStream_t stream) {
-    static bool attr_set = false;
-    auto fn = plane_kernel<T, E, K, FWD>;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
+// Planes one workgroup of a plane kernel takes at most (PSPFFT_PLANES_PER_WG,
+// default 8); the grid never goes below what the device holds at once.
+inline int planes_per_workgroup() {
+    static int v = 0;
+    if (v == 0) {
+        const char *e = std::getenv("PSPFFT_PLANES_PER_WG");
+        const int x = e ? std::atoi(e) : 0;
+        v = x >= 1 && x <= 1024 ? x : 8;
     }
+    return v;
+}
+
+// Grid: as many workgroups as the device holds at once (from the occupancy of
+// this kernel), or more when that would give a workgroup more planes than
+// planes_per_workgroup(); never more than one per plane.
+template <typename T, int E, int K, bool FWD>
+hipError_t launch_plane_kernel(const LaunchArgs &args, size_t lds, hipStream_t stream) {
+    constexpr int kMaxDevices = 64;
+    static int resident[kMaxDevices] = {0};
+    auto fn = plane_kernel<T, E, K, FWD>;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (resident[dev] == 0) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024);
+        if (e != hipSuccess) return e;
+        int per_cu = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, E * K * K, lds);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        resident[dev] = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    }
+    // at most planes_per_workgroup() planes each: more workgroups than the device
+    // holds at once leave room for kernels on other streams
+    const int per = planes_per_workgroup();
+    const int want = (args.nwg + per - 1) / per;
+    int grid = want > resident[dev] ? want : resident[dev];
+    if (grid > args.nwg) grid = args.nwg;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(E * K * K), lds, stream, args);
     return hipGetLastError();
 }
@@ -227,8 +358,8 @@ hipError_t launch_plane_k(bool fwd, const LaunchArgs &args, int grid, size_t lds
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
     if constexpr (plane_fits(prec, E, K)) {
         if (lds != plane_lds_bytes(prec, E, K)) return hipErrorInvalidValue;
-        return fwd ? launch_plane_kernel<T, E, K, true>(args, grid, lds, stream)
-                   : launch_plane_kernel<T, E, K, false>(args, grid, lds, stream);
+        return fwd ? launch_plane_kernel<T, E, K, true>(args, lds, stream)
+                   : launch_plane_kernel<T, E, K, false>(args, lds, stream);
     } else {
         return hipErrorInvalidValue;
     }

@@ -270,6 +270,15 @@ void destroy_plan(pspfft_plan_t p) {
     delete p;
 }
 
+// Every device array of a solve (source, potential, workspace, spectrum) is
+// addressable with 31-bit byte offsets.
+bool arrays_below_2gb(pspfft_plan_t p) {
+    const size_t lim = size_t(1) << 31;
+    const size_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+    const size_t r = real_size(p->prec);
+    return ws_bytes(p->n, p->prec) < lim && nx * ny * nz * r < lim && (nz + 1) * (ny + 1) * nx * r < lim;
+}
+
 // Lines (main, Nyquist) that a pass processes for one problem.
 void pass_lines(int mode, const int n[3], long &main, long &nyq) {
     const long nx = n[0], ny = n[1], nz = n[2];
@@ -370,9 +379,11 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d: %d problems in %d segments, %ld workgroups of %d threads, %zu B LDS",
                        mode, prec, E, K, args.count, args.nseg, wg, block, lds);
             // compile-time geometry when every line has two stages (L = E*K) and the
-            // workgroup holds the default number of lines
+            // workgroup holds the default number of lines; 32-bit offsets need
+            // every array below 2 GB
             bool fix = K > 1 && block == pspfft::default_tile(prec, row) * K;
-            for (size_t j = c0; j < c1 && fix; ++j) fix = plans[idx[j]]->host.ax[axis].nst == 2;
+            for (size_t j = c0; j < c1 && fix; ++j)
+                fix = plans[idx[j]]->host.ax[axis].nst == 2 && arrays_below_2gb(plans[idx[j]]);
             if (pspfft::launch_pass(mode, prec, E, K, fix, args, grid, block, lds, stream) != hipSuccess)
                 return PSPFFT_ERR_DEVICE;
         }
