@@ -119,7 +119,9 @@ struct LineFFT {
     // Transform the line whose positions t + NB*m the thread holds in v[m].
     // K = radix of the last stage (1: the whole line is one radix-E stage).
     // twl: stage twiddle tables in LDS, published by the first barrier.
-    template <int K>
+    // LEAD: open with a barrier so that earlier readers of the line's LDS
+    // region are done; a caller that has just passed a barrier can skip it.
+    template <int K, bool LEAD = true>
     static __device__ __forceinline__ void run(cx<T> *v, const AxisPlan &ax, cx<T> *lds, int ldsw,
                                                const cx<T> *twl, int c, int t) {
         const int NB = CNB ? CNB : ax.NB;
@@ -128,13 +130,13 @@ struct LineFFT {
         } else if constexpr (CNB != 0) {
             // two stages, radix E then K: the second has Ns = E and its twiddles
             // follow the E - 1 entries of the first
-            __syncthreads();  // earlier readers of LDS are done
+            if constexpr (LEAD) __syncthreads();  // earlier readers of LDS are done
             stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
             __syncthreads();
             gather(v, lds, ldsw, c, t, NB);
             stage<K, true, false, E>(v, E, 0u, twl + (E - 1), lds, ldsw, c, t, NB);
         } else {
-            __syncthreads();  // earlier readers of LDS are done
+            if constexpr (LEAD) __syncthreads();  // earlier readers of LDS are done
             stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
             const int last = ax.nst - 1;
             for (int s = 1; s < last; ++s) {

@@ -136,7 +136,8 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                 cx<T> v[E];
 #pragma unroll
                 for (int m = 0; m < E; ++m) v[m] = m < H ? s[m] : cx<T>{T(0), T(0)};
-                RowF::template run<K>(v, ax, lds, SP, twl, xc, xt);
+                // no leading barrier: the end of the previous plane has one
+                RowF::template run<K, false>(v, ax, lds, SP, twl, xc, xt);
                 // U[k] to the row (each thread writes the positions its last gather read)
                 cx<T> *row = lds + xc * SP;
 #pragma unroll
@@ -191,18 +192,15 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                 emit(w, 1);
             }
             __syncthreads();
-            // The first wave separates column 0: C = A + i B with A, B the transforms
-            // of the real columns kx = 0 and kx = n.
-            constexpr int NT = BLK < 64 ? BLK : 64;
-            if (tid < NT) {
-                for (int ky = tid; ky < 2 * n; ky += NT) {
-                    const int kp = ky == 0 ? 0 : 2 * n - ky;
-                    const cx<T> C = sep[ky];
-                    const cx<T> Cp = sep[kp];
-                    Wz[static_cast<size_t>(ky) * n] =
-                        cx<T>{static_cast<T>(0.5) * (C.x + Cp.x), static_cast<T>(0.5) * (C.y - Cp.y)};
-                    Wnz[ky] = cx<T>{static_cast<T>(0.5) * (C.y + Cp.y), static_cast<T>(-0.5) * (C.x - Cp.x)};
-                }
+            // Separate column 0: C = A + i B with A, B the transforms of the real
+            // columns kx = 0 and kx = n (one entry per thread).
+            for (int ky = tid; ky < 2 * n; ky += BLK) {
+                const int kp = ky == 0 ? 0 : 2 * n - ky;
+                const cx<T> C = sep[ky];
+                const cx<T> Cp = sep[kp];
+                Wz[static_cast<size_t>(ky) * n] =
+                    cx<T>{static_cast<T>(0.5) * (C.x + Cp.x), static_cast<T>(0.5) * (C.y - Cp.y)};
+                Wnz[ky] = cx<T>{static_cast<T>(0.5) * (C.y + Cp.y), static_cast<T>(-0.5) * (C.x - Cp.x)};
             }
             if (nxt >= args.nwg) break;
             pl = nxt;
@@ -236,6 +234,7 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
         };
         load_even(pl);
         stage_nyquist();
+        __syncthreads();  // twiddles and the first Nyquist column visible
         for (;;) {
             lanes();
             const uint32_t even_off = static_cast<uint32_t>((2 * yt * n + yc) * CSZ);
@@ -244,7 +243,8 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
             cx<T> o[E];  // odd rows, in flight while the even ones are transformed
 #pragma unroll
             for (int m = 0; m < E; ++m) o[m] = at<T>(Wz, even_off + (m * 2 * NB + 1) * n * CSZ);
-            __syncthreads();  // Nyquist column and twiddles visible
+            // the barrier before the loop or at the end of the previous plane
+            // published the Nyquist column and retired the readers of the plane
             {  // y step: column kx = 0 also carries kx = n (as Y0 + i Yn)
                 if (yc == 0) {
 #pragma unroll
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                         e[m] = cx<T>{e[m].x - a.y, e[m].y + a.x};
                     }
                 }
-                ColI::template run<K>(e, ax, lds, SP, twl, cp, yt);
+                ColI::template run<K, false>(e, ax, lds, SP, twl, cp, yt);
                 if (yc == 0) {
 #pragma unroll
                     for (int m = 0; m < E; ++m) {
