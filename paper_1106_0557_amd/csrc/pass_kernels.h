@@ -152,6 +152,39 @@ struct LineFFT {
     }
 };
 
+// Value of another lane of the wavefront (byte address src_lane*4), through the
+// LDS crossbar without LDS storage or a barrier.
+__device__ __forceinline__ float lane_read(int addr, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_read(int addr, double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Mirror partners of a packed real transform.  The NB (a power of two that
+// divides 64) threads of a row are consecutive lanes; thread t (lane `lane` of
+// the wavefront) holds positions k = t + NB*m of a length n = E*NB line.  p[m]
+// receives the value at position (n - k) mod n, which thread (NB - t) mod NB
+// holds in register E - 1 - m (t > 0) and thread 0 holds in its own register
+// (E - m) mod E.
+template <typename T, int E, int NB>
+__device__ __forceinline__ void mirror_partners(const cx<T> *v, cx<T> *p, int t, int lane) {
+    if constexpr (NB == 1) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) p[m] = v[(E - m) % E];
+    } else {
+        const int addr = (lane - t + ((NB - t) & (NB - 1))) << 2;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const cx<T> d = t == 0 ? v[(E - m) % E] : v[E - 1 - m];  // what this lane sends
+            p[m] = cx<T>{lane_read(addr, d.x), lane_read(addr, d.y)};
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void copy_to_lds(cx<T> *dst, const void *src, int count) {
     const cx<T> *s = static_cast<const cx<T> *>(src);
@@ -278,25 +311,34 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 else v[m] = cx<T>{T(0), T(0)};
             }
             FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
-            // split: X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k])
-            __syncthreads();
-            {
+            // split: X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k]).
+            // Partners U[n-k]: from the mirror lane of the row with compile-time
+            // geometry, else through the row in LDS.
+            cx<T> wp[E];
+            if constexpr (FIX) {
+                mirror_partners<T, E, K>(v, wp, t, tid & 63);
+            } else {
+                __syncthreads();
                 cx<T> *row = lds + c * ldsw;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int P = t + NB * m;
                     row[P + (P >> 4)] = v[m];
                 }
-            }
-            __syncthreads();
-            if (active) {
-                const cx<T> *row = lds + c * ldsw;
+                __syncthreads();
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int k = t + NB * m;
                     const int kp = k == 0 ? 0 : L - k;
+                    wp[m] = row[kp + (kp >> 4)];
+                }
+            }
+            if (active) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int k = t + NB * m;
                     const cx<T> u = v[m];
-                    const cx<T> w = row[kp + (kp >> 4)];
+                    const cx<T> w = wp[m];
                     const cx<T> a = {static_cast<T>(0.5) * (u.x + w.x), static_cast<T>(0.5) * (u.y - w.y)};
                     const cx<T> b = {static_cast<T>(0.5) * (u.x - w.x), static_cast<T>(0.5) * (u.y + w.y)};
                     const cx<T> eb = cmul(post[k], b);
@@ -314,30 +356,38 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             }
             cx<T> xn = {T(0), T(0)};
             if (active) xn = *wnyq;
-            {
+            // partners X[n-k] (X[n] for k = 0): mirror lane, or through the row in LDS
+            cx<T> wp[E];
+            if constexpr (FIX) {
+                mirror_partners<T, E, K>(v, wp, t, tid & 63);
+                __syncthreads();  // post table and twiddles visible
+            } else {
                 cx<T> *row = lds + c * ldsw;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int P = t + NB * m;
                     row[P + (P >> 4)] = v[m];
                 }
-            }
-            __syncthreads();  // row values, post table and twiddles visible
-            {
-                const cx<T> *row = lds + c * ldsw;
+                __syncthreads();  // row values, post table and twiddles visible
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int k = t + NB * m;
-                    const int kp = L - k;
-                    const cx<T> a = v[m];
-                    const cx<T> b = k == 0 ? xn : row[kp + (kp >> 4)];
-                    const cx<T> sm = {a.x + b.x, a.y - b.y};
-                    const cx<T> df = {a.x - b.x, a.y + b.y};
-                    const cx<T> ed = cmulc(df, post[k]);
-                    v[m] = cx<T>{sm.x - ed.y, sm.y + ed.x};
+                    const int kp = k == 0 ? 0 : L - k;  // k = 0 takes X[n] below
+                    wp[m] = row[kp + (kp >> 4)];
                 }
             }
-            FFT_I::template run<K>(v, ax, lds, ldsw, twl, c, t);
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int k = t + NB * m;
+                const cx<T> a = v[m];
+                const cx<T> b = k == 0 ? xn : wp[m];
+                const cx<T> sm = {a.x + b.x, a.y - b.y};
+                const cx<T> df = {a.x - b.x, a.y + b.y};
+                const cx<T> ed = cmulc(df, post[k]);
+                v[m] = cx<T>{sm.x - ed.y, sm.y + ed.x};
+            }
+            // with the mirror lanes nothing of the row is in LDS yet: no leading barrier
+            FFT_I::template run<K, !FIX>(v, ax, lds, ldsw, twl, c, t);
             if (active) {
 #pragma unroll
                 for (int m = 0; m < H; ++m) fld[m] = v[m];

@@ -138,28 +138,24 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                 for (int m = 0; m < E; ++m) v[m] = m < H ? s[m] : cx<T>{T(0), T(0)};
                 // no leading barrier: the end of the previous plane has one
                 RowF::template run<K, false>(v, ax, lds, SP, twl, xc, xt);
-                // U[k] to the row (each thread writes the positions its last gather read)
-                cx<T> *row = lds + xc * SP;
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int P = xt + NB * m;
-                    row[P + (P >> 4)] = v[m];
-                }
-                __syncthreads();
-                // X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k])
+                // X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k]); the
+                // partners U[n-k] come from the mirror lane of the row
+                cx<T> wp[E];
+                mirror_partners<T, E, NB>(v, wp, xt, tid & 63);
+                if constexpr (K == 1) __syncthreads();  // post table visible
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int k = xt + NB * m;
-                    const int kp = k == 0 ? 0 : n - k;
                     const cx<T> u = v[m];
-                    const cx<T> w = row[kp + (kp >> 4)];
+                    const cx<T> w = wp[m];
                     const cx<T> a = {static_cast<T>(0.5) * (u.x + w.x), static_cast<T>(0.5) * (u.y - w.y)};
                     const cx<T> b = {static_cast<T>(0.5) * (u.x - w.x), static_cast<T>(0.5) * (u.y + w.y)};
                     const cx<T> eb = cmul(post[k], b);
                     v[m] = cx<T>{a.x + eb.y, a.y - eb.x};
                     if (m == 0 && xt == 0) v[m].y = u.x - u.y;  // X[0] is real: its imaginary slot takes X[n]
                 }
-                __syncthreads();  // partner reads done
+                // to the row: each thread writes the positions its last gather read
+                cx<T> *row = lds + xc * SP;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int P = xt + NB * m;
