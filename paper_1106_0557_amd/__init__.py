@@ -207,6 +207,18 @@ def solve_batched(workspaces: Sequence[Workspace], S: Sequence[torch.Tensor], Ph
                "pspfft_solve_batched")
 
 
+def pass_batched_ptrs(which: int, plans: Sequence[int], workspaces: Sequence[int], S: Sequence[int] | None,
+                      Phi: Sequence[int] | None, stream_handle: int = 0) -> None:
+    """``pspfft_pass_batched`` on raw handles and device pointers, for callers
+    (the serving loop) that validated their tensors once when they took them."""
+    lib = _lib.load()
+    n = len(workspaces)
+    _lib.check(lib.pspfft_pass_batched(int(which), n, _lib.ptr_array(plans), _lib.ptr_array(workspaces),
+                                       _lib.ptr_array(S) if S is not None else None,
+                                       _lib.ptr_array(Phi) if Phi is not None else None, stream_handle),
+               f"pspfft_pass_batched({which})")
+
+
 def pass_batched(which: int, workspaces: Sequence[Workspace], S=None, Phi=None, stream=None) -> None:
     """``pspfft_pass_batched``: one pass of the solve for every listed problem."""
     if which == PASS_X_FWD:

@@ -102,7 +102,5 @@ def check(status: int, what: str) -> None:
 
 
 def ptr_array(values):
-    arr = (ctypes.c_void_p * max(1, len(values)))()
-    for i, v in enumerate(values):
-        arr[i] = v
-    return arr
+    values = list(values)
+    return (ctypes.c_void_p * max(1, len(values)))(*values)

@@ -135,7 +135,7 @@ __host__ __device__ constexpr bool plane_fits(int prec, int E, int K) {
 // K is the radix of the last stage of the pass axis (1 for a single stage).
 // The plane launchers run the forward (fwd) or inverse fused kernel with n*K threads.
 #define PSPFFT_DECLARE_FAMILY(NAME, PLANE)                                                          \
-    hipError_t NAME(int mode, int K, bool fix, const LaunchArgs &args, int grid, int block,         \
+    hipError_t NAME(int mode, int K, int fix, const LaunchArgs &args, int grid, int block,          \
                     size_t lds, hipStream_t stream);                                                \
     hipError_t PLANE(bool fwd, int K, const LaunchArgs &args, int grid, size_t lds, hipStream_t stream);
 PSPFFT_DECLARE_FAMILY(launch_f32_e16, plane_f32_e16)
@@ -148,7 +148,7 @@ PSPFFT_DECLARE_FAMILY(launch_f64_e24, plane_f64_e24)
 PSPFFT_DECLARE_FAMILY(launch_f64_e36, plane_f64_e36)
 #undef PSPFFT_DECLARE_FAMILY
 
-inline hipError_t launch_pass(int mode, int prec, int E, int K, bool fix, const LaunchArgs &args, int grid,
+inline hipError_t launch_pass(int mode, int prec, int E, int K, int fix, const LaunchArgs &args, int grid,
                               int block, size_t lds, hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
     switch (prec * 100 + E) {

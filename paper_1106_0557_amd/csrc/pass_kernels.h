@@ -29,7 +29,8 @@
 namespace pspfft {
 
 // CNB, CLDSW: threads per line and LDS stride when known at compile time (a
-// two-stage line, L = E*K, in a workgroup of the default tile), else 0.
+// two-stage line, L = E*K and CNB = K, or a three-stage line with radices E, M,
+// K, L = E*M*K and CNB = M*K, in a workgroup of the default tile), else 0.
 template <typename T, int E, int DIR, bool ROW, int CNB = 0, int CLDSW = 0>
 struct LineFFT {
     static constexpr int M = E & -E;  // radix of the middle stages
@@ -127,7 +128,7 @@ struct LineFFT {
         const int NB = CNB ? CNB : ax.NB;
         if constexpr (K == 1) {
             stage<E, false, false>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
-        } else if constexpr (CNB != 0) {
+        } else if constexpr (CNB == K) {
             // two stages, radix E then K: the second has Ns = E and its twiddles
             // follow the E - 1 entries of the first
             if constexpr (LEAD) __syncthreads();  // earlier readers of LDS are done
@@ -135,6 +136,19 @@ struct LineFFT {
             __syncthreads();
             gather(v, lds, ldsw, c, t, NB);
             stage<K, true, false, E>(v, E, 0u, twl + (E - 1), lds, ldsw, c, t, NB);
+        } else if constexpr (CNB != 0) {
+            // three stages, radices E, M, K (CNB = M*K): Ns = 1, E, E*M; the
+            // twiddle tables follow one another (E - 1 and E*(M - 1) entries)
+            static_assert(CNB == M * K, "compile-time lines have two or three stages");
+            if constexpr (LEAD) __syncthreads();
+            stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
+            __syncthreads();
+            gather(v, lds, ldsw, c, t, NB);
+            __syncthreads();
+            stage<M, true, true, E>(v, E, 0u, twl + (E - 1), lds, ldsw, c, t, NB);
+            __syncthreads();
+            gather(v, lds, ldsw, c, t, NB);
+            stage<K, true, false, E * M>(v, E * M, 0u, twl + (E - 1) + E * (M - 1), lds, ldsw, c, t, NB);
         } else {
             if constexpr (LEAD) __syncthreads();  // earlier readers of LDS are done
             stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
@@ -223,10 +237,11 @@ __device__ __forceinline__ LinePtr<T, OFF32> line_ptr(const void *base, size_t l
     return LinePtr<T, OFF32>{const_cast<char *>(static_cast<const char *>(base)), lane_elems * esz, step_elems * esz};
 }
 
-// FIX: every problem of the launch has a two-stage line (L = E*K, NB = K), the
-// workgroup holds the default number of lines, so the geometry is compile-time,
-// and every array is below 2 GB, so addresses use 32-bit lane offsets.
-template <typename T, int E, int K, int MODE, bool FIX>
+// FIX (2 or 3): every problem of the launch has lines of that many stages with
+// radices E, (M,) K, the workgroup holds the default number of lines, so the
+// geometry is compile-time, and every array is below 2 GB, so addresses use
+// 32-bit lane offsets.  FIX = 0: geometry from the plan at run time.
+template <typename T, int E, int K, int MODE, int FIX>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pass_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
@@ -234,8 +249,9 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr int H = E / 2;  // registers m < H hold the first half of the line
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
     constexpr int FTILE = default_tile(sizeof(T) == 4 ? 0 : 1, ROW);
-    constexpr int CNB = FIX ? K : 0;
-    constexpr int CLDSW = FIX ? (ROW ? row_stride(E * K, K, CSZ) : FTILE + 1) : 0;
+    constexpr int CNB = FIX == 2 ? K : (FIX == 3 ? (E & -E) * K : 0);
+    constexpr int CL = E * CNB;  // line length when compile-time
+    constexpr int CLDSW = FIX ? (ROW ? row_stride(CL, CNB, CSZ) : FTILE + 1) : 0;
     using FFT_F = LineFFT<T, E, -1, ROW, CNB, CLDSW>;
     using FFT_I = LineFFT<T, E, +1, ROW, CNB, CLDSW>;
 
@@ -264,9 +280,9 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr int axis = ROW ? 0 : (MODE == Z_CONV ? 2 : 1);
     const AxisPlan &ax = pl.ax[axis];
     const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
-    const int NB = FIX ? K : ax.NB;
-    const int L = FIX ? E * K : ax.L;
-    const int block = FIX ? FTILE * K : static_cast<int>(blockDim.x);
+    const int NB = FIX ? CNB : ax.NB;
+    const int L = FIX ? CL : ax.L;
+    const int block = FIX ? FTILE * CNB : static_cast<int>(blockDim.x);
     const int tile = FIX ? FTILE : block / NB;  // lines per workgroup (power of two)
     const int tid = threadIdx.x;
     int c, t;
@@ -278,7 +294,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         t = tid >> __builtin_ctz(tile);
     }
     const int ldsw = FIX ? CLDSW : (ROW ? row_stride(L, NB, CSZ) : tile + 1);
-    cx<T> *twl = lds + (FIX ? data_elems(ROW, E * K, K, FTILE * K, CSZ) : data_elems(ROW, L, NB, block, CSZ));
+    cx<T> *twl = lds + (FIX ? data_elems(ROW, CL, CNB, FTILE * CNB, CSZ) : data_elems(ROW, L, NB, block, CSZ));
     copy_to_lds<T>(twl, ax.tw, ax.ntw);
 
     const bool nyq = local >= sg.wg_main;
@@ -301,9 +317,9 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         const size_t wrow = (static_cast<size_t>(z) * 2 * ny + y) * nx;  // row start in W (elements)
         cx<T> *wnyq = Wn + static_cast<size_t>(z) * 2 * ny + y;
         // thread t's positions t + NB*m of row g of S / Phi (pairs of reals) and of W
-        const auto fld = line_ptr<T, FIX>(MODE == X_FWD ? pa.S : pa.Phi,
+        const auto fld = line_ptr<T, FIX != 0>(MODE == X_FWD ? pa.S : pa.Phi,
                                           static_cast<size_t>(active ? g : 0) * nx / 2 + t, NB, CSZ);
-        const auto wl = line_ptr<T, FIX>(W, wrow + t, NB, CSZ);
+        const auto wl = line_ptr<T, FIX != 0>(W, wrow + t, NB, CSZ);
         if constexpr (MODE == X_FWD) {
 #pragma unroll
             for (int m = 0; m < E; ++m) {
@@ -316,7 +332,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             // geometry, else through the row in LDS.
             cx<T> wp[E];
             if constexpr (FIX) {
-                mirror_partners<T, E, K>(v, wp, t, tid & 63);
+                mirror_partners<T, E, CNB>(v, wp, t, tid & 63);
             } else {
                 __syncthreads();
                 cx<T> *row = lds + c * ldsw;
@@ -359,7 +375,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             // partners X[n-k] (X[n] for k = 0): mirror lane, or through the row in LDS
             cx<T> wp[E];
             if constexpr (FIX) {
-                mirror_partners<T, E, K>(v, wp, t, tid & 63);
+                mirror_partners<T, E, CNB>(v, wp, t, tid & 63);
                 __syncthreads();  // post table and twiddles visible
             } else {
                 cx<T> *row = lds + c * ldsw;
@@ -387,7 +403,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 v[m] = cx<T>{sm.x - ed.y, sm.y + ed.x};
             }
             // with the mirror lanes nothing of the row is in LDS yet: no leading barrier
-            FFT_I::template run<K, !FIX>(v, ax, lds, ldsw, twl, c, t);
+            FFT_I::template run<K, FIX == 0>(v, ax, lds, ldsw, twl, c, t);
             if (active) {
 #pragma unroll
                 for (int m = 0; m < H; ++m) fld[m] = v[m];
@@ -437,7 +453,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         // this thread's position t; position t + NB*m is m*NB*es elements further.
         // An inactive line (past the end of a partial tile) reads in-bounds
         // dummies from the start of the array and stores nothing.
-        const auto lane = line_ptr<T, FIX>(arr, active ? base + t * es : 0, static_cast<size_t>(NB) * es, CSZ);
+        const auto lane = line_ptr<T, FIX != 0>(arr, active ? base + t * es : 0, static_cast<size_t>(NB) * es, CSZ);
         // Forward transforms read only the stored half (m < H); inverse ones
         // read the whole line.
         constexpr int nload = (MODE == Y_INV) ? E : H;
@@ -488,7 +504,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     }
 }
 
-template <typename T, int E, int K, int MODE, bool FIX>
+template <typename T, int E, int K, int MODE, int FIX>
 hipError_t launch_kernel(const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
     static bool attr_set = false;
     auto fn = pass_kernel<T, E, K, MODE, FIX>;
@@ -502,7 +518,7 @@ hipError_t launch_kernel(const LaunchArgs &args, int grid, int block, size_t lds
     return hipGetLastError();
 }
 
-template <typename T, int E, int K, bool FIX>
+template <typename T, int E, int K, int FIX>
 hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
     switch (mode) {
         case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
@@ -514,19 +530,28 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
     }
 }
 
+// fix: 0 (run-time geometry), 2 or 3 (compile-time lines of that many stages).
+// Three-stage instances exist where a default-tile workgroup of M*K threads per
+// line fits the family's largest workgroup.
 template <typename T, int E, int K>
-hipError_t launch_fix(int mode, bool fix, const LaunchArgs &args, int grid, int block, size_t lds,
+hipError_t launch_fix(int mode, int fix, const LaunchArgs &args, int grid, int block, size_t lds,
                       hipStream_t stream) {
+    constexpr int prec = sizeof(T) == 4 ? 0 : 1;
+    constexpr int M = E & -E;
     if constexpr (K > 1) {
-        if (fix) return launch_mode<T, E, K, true>(mode, args, grid, block, lds, stream);
+        if (fix == 2) return launch_mode<T, E, K, 2>(mode, args, grid, block, lds, stream);
+        if constexpr (default_tile(prec, false) * M * K <= max_block_for(prec, E)) {
+            if (fix == 3) return launch_mode<T, E, K, 3>(mode, args, grid, block, lds, stream);
+        }
     }
-    return launch_mode<T, E, K, false>(mode, args, grid, block, lds, stream);
+    if (fix != 0) return hipErrorInvalidValue;
+    return launch_mode<T, E, K, 0>(mode, args, grid, block, lds, stream);
 }
 
 // All last-stage radices a family can have: 1 (single stage) and the powers of
 // two up to the middle radix.
 template <typename T, int E>
-hipError_t launch_family(int mode, int K, bool fix, const LaunchArgs &args, int grid, int block, size_t lds,
+hipError_t launch_family(int mode, int K, int fix, const LaunchArgs &args, int grid, int block, size_t lds,
                          hipStream_t stream) {
     constexpr int M = E & -E;
     switch (K) {

@@ -377,7 +377,7 @@ hipError_t launch_plane_family(bool fwd, int K, const LaunchArgs &args, int grid
 // One translation unit per (precision, family) keeps compiles parallel.
 #define PSPFFT_FAMILY(T, E, NAME, PLANE)                                                            \
     namespace pspfft {                                                                              \
-    hipError_t NAME(int mode, int K, bool fix, const LaunchArgs &args, int grid, int block,         \
+    hipError_t NAME(int mode, int K, int fix, const LaunchArgs &args, int grid, int block,          \
                     size_t lds, hipStream_t stream) {                                               \
         return launch_family<T, E>(mode, K, fix, args, grid, block, lds, stream);                   \
     }                                                                                               \

@@ -376,14 +376,25 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
             args.xcd_remap = xcd_remap_mode(mode);
             const long align = args.xcd_remap == 1 ? 8 : (args.xcd_remap == 2 ? 64 : 1);
             const int grid = static_cast<int>((wg + align - 1) / align * align);
-            PSPFFT_LOG(3, "pass %d prec %d E %d K %d: %d problems in %d segments, %ld workgroups of %d threads, %zu B LDS",
-                       mode, prec, E, K, args.count, args.nseg, wg, block, lds);
-            // compile-time geometry when every line has two stages (L = E*K) and the
-            // workgroup holds the default number of lines; 32-bit offsets need
-            // every array below 2 GB
-            bool fix = K > 1 && block == pspfft::default_tile(prec, row) * K;
-            for (size_t j = c0; j < c1 && fix; ++j)
-                fix = plans[idx[j]]->host.ax[axis].nst == 2 && arrays_below_2gb(plans[idx[j]]);
+            // compile-time geometry when every line has two stages (radices E, K)
+            // or three (E, M, K), the workgroup holds the default number of lines,
+            // and every array is below 2 GB (32-bit offsets)
+            const int M = E & -E;
+            int fix = 0;
+            if (K > 1) {
+                const AxisPlan &a0 = plans[idx[c0]]->host.ax[axis];
+                if (a0.nst == 2) fix = 2;
+                else if (a0.nst == 3 && a0.R[1] == M) fix = 3;
+                const int cnb = fix == 2 ? K : M * K;
+                if (fix && block != pspfft::default_tile(prec, row) * cnb) fix = 0;
+                if (fix == 3 && pspfft::default_tile(prec, false) * cnb > pspfft::max_block_for(prec, E)) fix = 0;
+                for (size_t j = c0; j < c1 && fix; ++j) {
+                    const AxisPlan &ax = plans[idx[j]]->host.ax[axis];
+                    if (ax.nst != a0.nst || ax.NB != cnb || !arrays_below_2gb(plans[idx[j]])) fix = 0;
+                }
+            }
+            PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "
+                          "threads, %zu B LDS", mode, prec, E, K, fix, args.count, args.nseg, wg, block, lds);
             if (pspfft::launch_pass(mode, prec, E, K, fix, args, grid, block, lds, stream) != hipSuccess)
                 return PSPFFT_ERR_DEVICE;
         }

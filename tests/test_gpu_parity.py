@@ -174,6 +174,27 @@ def test_solve_matches_oracle(n):
     assert r32["rel_l2"] <= FP32_TOL
 
 
+# Lines of three stages (radices E, M, K) with compile-time geometry: z lines of
+# 512 (16*16*2), 1024 (16*16*4), 576 (36*4*4), 320 (20*4*4); y lines of 384
+# (24*8*2), 288 (36*4*2), 160 (20*4*2); x rows of 512 and 384.
+THREE_STAGE = [(16, 8, 256), (16, 8, 512), (16, 8, 288), (16, 192, 8), (16, 144, 8), (20, 80, 160),
+               (512, 8, 8), (384, 8, 8)]
+
+
+@pytest.mark.parametrize("n", THREE_STAGE)
+def test_three_stage_lines_match_oracle(n):
+    say(f"[three-stage] n={n}")
+    h = (0.02, 0.03, 0.025)
+    S = sources.random_field(n, seed=sum(n) + 1).numpy()
+    ref = oracle.solve_fft(S, h)
+    got64 = gpu_solve(n, h, S, torch.float64)
+    got32 = gpu_solve(n, h, S, torch.float32)
+    r64, r32 = norms.report(got64, ref), norms.report(got32, ref)
+    say(f"  fp64 {r64}\n  fp32 {r32}")
+    assert r64["rel_l2"] <= FP64_TOL and r64["rel_max"] <= FP64_TOL
+    assert r32["rel_l2"] <= FP32_TOL
+
+
 def test_zero_source_gives_zero_potential():
     say("[zero source]")
     n = (24, 16, 20)

@@ -27,9 +27,10 @@ class FakeToken:
 
 
 class FakeExecutor:
-    def __init__(self, polls=2, compute=False):
+    def __init__(self, polls=2, compute=False, fused_sizes=()):
         self.polls = polls
         self.compute = compute
+        self.fused_sizes = set(fused_sizes)  # meshes whose plans skip the y passes
         self.pool = {}
         self.log = []          # (step, pass, request index)
         self.step_no = 0
@@ -45,6 +46,9 @@ class FakeExecutor:
 
     def key(self, req):
         return (req.n, req.h)
+
+    def active_passes(self, req):
+        return (0, 2, 4) if req.n[0] in self.fused_sizes else tuple(range(NUM_PASSES))
 
     def has_pooled(self, req):
         return bool(self.pool.get(self.key(req)))
@@ -108,6 +112,25 @@ def test_every_request_gets_each_pass_once_in_order():
         assert [p for _, p in seq] == list(range(NUM_PASSES))
         steps = [s for s, _ in seq]
         assert steps == sorted(steps) and len(set(steps)) == NUM_PASSES  # one pass per step
+
+
+def test_fused_requests_skip_the_y_passes_beside_five_pass_ones():
+    ex = FakeExecutor(fused_sizes=(16, 32))
+    srv = Server(ex, budget_bytes=1 << 40, max_inflight=5)
+    sizes = [16, 24, 32, 48, 16, 24, 32, 16, 48, 24]
+    fin = srv.run_trace(_reqs(sizes), realtime=False)
+    assert len(fin) == len(sizes) and all(r.done and not r.rejected for r in fin)
+    for i, n in enumerate(sizes):
+        seq = [(s, p) for (s, p, r) in ex.log if r == i]
+        want = [0, 2, 4] if n in (16, 32) else [0, 1, 2, 3, 4]
+        assert [p for _, p in seq] == want, (i, n, seq)
+        steps = [s for s, _ in seq]
+        assert steps == list(range(steps[0], steps[0] + len(want)))  # one pass per step, no gaps
+    # steps mix fused and five-pass requests at the same pass
+    by_step = {}
+    for s, p, r in ex.log:
+        by_step.setdefault((s, p), set()).add(sizes[r] in (16, 32))
+    assert any(len(v) == 2 for v in by_step.values())
 
 
 def test_admission_respects_budget_and_slots():
