@@ -120,6 +120,19 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
 /* 1 if the plan runs fused x-y plane kernels, 0 otherwise (and for NULL). */
 int pspfft_plan_fused(pspfft_plan_t plan);
 
+/*
+ * Workspace layout, for code that reads a workspace between passes (tests,
+ * debugging).  A workspace of this plan holds, in the plan's complex type,
+ *   W  = [nz / B][2 ny][B][nx]  then, 256-byte aligned,  Wn = [nz][2 ny],
+ * where B = pspfft_workspace_ztile(plan) (a power of two up to 16 dividing nz):
+ * the value at (z, ky, kx < nx) is W[z / B][ky][z % B][kx] and the one at kx = nx
+ * is Wn[z][ky].  Grouping B z planes keeps each z line of the z pass within
+ * nz / B memory regions.  After the forward x and y passes it holds the
+ * transform along x and y of the zero-padded source for z < nz; after the z pass
+ * the same after the convolution.  Returns 0 for NULL.
+ */
+int pspfft_workspace_ztile(pspfft_plan_t plan);
+
 /* Release a plan and everything it owns (Sec. 3.2, Destroy).  Synchronises the
  * device first.  NULL returns PSPFFT_ERR_INVALID_ARGUMENT. */
 pspfft_status pspfft_destroy(pspfft_plan_t plan);

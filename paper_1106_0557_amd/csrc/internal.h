@@ -1,9 +1,15 @@
 // internal.h -- data structures shared by the HIP kernels and the host runtime.
 //
 // Workspace layout of one in-flight solve (complex values of the precision):
-//   W  : [z < nz][ky < 2ny][kx < nx]   main part, row stride nx (rows aligned)
-//   Wn : [z < nz][ky < 2ny]            the kx = nx (Nyquist) column, split off so
-//                                      that every row of W has an aligned length
+//   W  : [z / B][ky < 2ny][z % B][kx < nx]   main part in tiles of B z planes
+//                                            (rows of nx values, aligned)
+//   Wn : [z < nz][ky < 2ny]                  the kx = nx (Nyquist) column, split
+//                                            off so that every row of W is aligned
+// B (DevPlan::zb, a power of two up to 16 that divides the z lines' threads per
+// line; 1 unless a z plane spans 4 MB or more) keeps the z lines of the z pass
+// within nz/B regions of B rows instead of nz planes far apart, which the address
+// translation caches cannot hold for large meshes.  Row (z, ky) starts at element
+// ((z/B)*2ny + ky)*B*nx + (z%B)*nx.
 // The x pass writes rows ky = y < ny of every z plane; the y pass fills all 2ny
 // rows; the z pass works in place on z < nz; the inverse y pass leaves rows
 // y < ny; the inverse x pass reads them.  The upper z half of the doubled mesh
@@ -49,6 +55,7 @@ struct AxisPlan {
 
 struct DevPlan {
     int nx, ny, nz, prec;  // prec: 0 = FP32, 1 = FP64
+    int zb;                // z planes per tile of the workspace
     AxisPlan ax[3];        // x, y, z
     const void *G;         // spectrum, main part
     const void *Gn;        // spectrum, kx = nx
@@ -83,6 +90,12 @@ struct LaunchArgs {
 };
 
 enum PassMode { X_FWD = 0, Y_FWD = 1, Z_CONV = 2, Y_INV = 3, X_INV = 4 };
+
+// Start (in elements) of workspace row (z, ky).
+__host__ __device__ inline size_t w_row(int z, int ky, int ny, int nx, int zb) {
+    const int sh = __builtin_ctz(static_cast<unsigned>(zb));  // zb is a power of two
+    return ((static_cast<size_t>(z >> sh) * 2 * ny + ky) * zb + (z & (zb - 1))) * static_cast<size_t>(nx);
+}
 
 // LDS layout of a workgroup (complex elements), identical on host and device.
 // Column passes keep element (line c, position P) at P*(tile+1) + c; row passes

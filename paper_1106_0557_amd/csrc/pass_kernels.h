@@ -215,7 +215,7 @@ __device__ __forceinline__ const gbl<U> *as_global(const U *p) {
 }
 
 // Element m of a line: base + lane + m*step bytes.  OFF32 (set by the host when
-// every array of the launch is below 2 GB): the offset lane + m*step is
+// every array of the launch is below 4 GB): the offset lane + m*step is
 // computed in 32 bits and added to the workgroup-uniform base, so each access
 // is a scalar base plus one 32-bit vector offset.
 template <typename T, bool OFF32>
@@ -239,7 +239,7 @@ __device__ __forceinline__ LinePtr<T, OFF32> line_ptr(const void *base, size_t l
 
 // FIX (2 or 3): every problem of the launch has lines of that many stages with
 // radices E, (M,) K, the workgroup holds the default number of lines, so the
-// geometry is compile-time, and every array is below 2 GB, so addresses use
+// geometry is compile-time, and every array is below 4 GB, so addresses use
 // 32-bit lane offsets.  FIX = 0: geometry from the plan at run time.
 template <typename T, int E, int K, int MODE, int FIX>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pass_kernel(const LaunchArgs args) {
@@ -314,7 +314,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         const bool active = g < nrows;
         const int z = active ? g / ny : 0;
         const int y = g - z * ny;
-        const size_t wrow = (static_cast<size_t>(z) * 2 * ny + y) * nx;  // row start in W (elements)
+        const size_t wrow = w_row(z, y, ny, nx, pl.zb);  // row start in W (elements)
         cx<T> *wnyq = Wn + static_cast<size_t>(z) * 2 * ny + y;
         // thread t's positions t + NB*m of row g of S / Phi (pairs of reals) and of W
         const auto fld = line_ptr<T, FIX != 0>(MODE == X_FWD ? pa.S : pa.Phi,
@@ -425,8 +425,8 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 kx = g - vrow * nx;
                 ky = vrow == 0 ? 0 : (vrow == 2 * ny - 1 ? ny : ((vrow & 1) ? (vrow + 1) >> 1 : 2 * ny - (vrow >> 1)));
                 arr = W;
-                base = static_cast<size_t>(ky) * nx + kx;
-                es = static_cast<size_t>(2) * ny * nx;
+                base = static_cast<size_t>(ky) * pl.zb * nx + kx;
+                es = static_cast<size_t>(2) * ny * nx;  // per z tile of the threads' positions, see below
             } else {
                 active = g < 2 * ny;
                 ky = g;
@@ -441,8 +441,8 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 const int z = active ? g / nx : 0;
                 kx = g - z * nx;
                 arr = W;
-                base = static_cast<size_t>(z) * 2 * ny * nx + kx;
-                es = nx;
+                base = w_row(z, 0, ny, nx, pl.zb) + kx;
+                es = static_cast<size_t>(pl.zb) * nx;
             } else {
                 active = g < nz;
                 arr = Wn;
@@ -451,9 +451,18 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             }
         }
         // this thread's position t; position t + NB*m is m*NB*es elements further.
-        // An inactive line (past the end of a partial tile) reads in-bounds
-        // dummies from the start of the array and stores nothing.
-        const auto lane = line_ptr<T, FIX != 0>(arr, active ? base + t * es : 0, static_cast<size_t>(NB) * es, CSZ);
+        // z lines of the main part: z = t + NB*m sits in tile z/zb at row z%zb,
+        // and zb divides NB, so the thread's offset is fixed and each m moves
+        // NB/zb tiles of 2ny*zb*nx elements.  An inactive line (past the end of
+        // a partial tile) reads in-bounds dummies from the start of the array and
+        // stores nothing.
+        size_t lane_off = base + t * es;
+        if (MODE == Z_CONV && !nyq) {
+            const int zb = pl.zb;
+            const int sh = __builtin_ctz(static_cast<unsigned>(zb));
+            lane_off = base + (static_cast<size_t>(t >> sh) * 2 * ny * zb + (t & (zb - 1))) * nx;
+        }
+        const auto lane = line_ptr<T, FIX != 0>(arr, active ? lane_off : 0, static_cast<size_t>(NB) * es, CSZ);
         // Forward transforms read only the stored half (m < H); inverse ones
         // read the whole line.
         constexpr int nload = (MODE == Y_INV) ? E : H;

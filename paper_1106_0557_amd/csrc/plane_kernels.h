@@ -111,9 +111,10 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
     };
     lanes();
 
-    auto W_of = [&](const PlaneRef &r) {
-        return static_cast<cx<T> *>(r.pa->W) + static_cast<size_t>(r.z) * 2 * n * n;
-    };
+    // z plane of the workspace: fused plans have untiled workspaces (one z plane
+    // per tile), so rows ky are n values apart
+    auto W_of = [&](const PlaneRef &r) { return static_cast<cx<T> *>(r.pa->W) + static_cast<size_t>(r.z) * 2 * n * n; };
+    auto rs_of = [&](const PlaneRef &) { return static_cast<uint32_t>(n * CSZ); };
     auto Wn_of = [&](const PlaneRef &r) { return static_cast<cx<T> *>(r.pa->Wn) + static_cast<size_t>(r.z) * 2 * n; };
 
     if constexpr (FWD) {
@@ -128,8 +129,9 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
         for (;;) {
             lanes();
             load_src(pl);
-            const uint32_t wy_off = static_cast<uint32_t>((2 * yt * n + yc) * CSZ);  // W row 2*yt, column yc
             const PlaneRef r = plane_ref(args, pl);
+            const uint32_t rs = rs_of(r);                                     // W row stride (bytes)
+            const uint32_t wy_off = static_cast<uint32_t>(2 * yt) * rs + yc * CSZ;  // W row 2*yt, column yc
             cx<T> *Wz = W_of(r);
             cx<T> *Wnz = Wn_of(r);
             {  // x step
@@ -179,7 +181,7 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                         for (int m = 0; m < E; ++m) sep[2 * (yt + NB * m) + parity] = q[m];
                     } else {
 #pragma unroll
-                        for (int m = 0; m < E; ++m) at<T>(Wz, wy_off + (m * 2 * NB + parity) * n * CSZ) = q[m];
+                        for (int m = 0; m < E; ++m) at<T>(Wz, wy_off + (m * 2 * NB + parity) * rs) = q[m];
                     }
                 };
                 ColF::template run<K>(v, ax, lds, SP, twl, cp, yt);  // Y[2j]
@@ -194,7 +196,7 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                 const int kp = ky == 0 ? 0 : 2 * n - ky;
                 const cx<T> C = sep[ky];
                 const cx<T> Cp = sep[kp];
-                Wz[static_cast<size_t>(ky) * n] =
+                at<T>(Wz, ky * rs) =
                     cx<T>{static_cast<T>(0.5) * (C.x + Cp.x), static_cast<T>(0.5) * (C.y - Cp.y)};
                 Wnz[ky] = cx<T>{static_cast<T>(0.5) * (C.y + Cp.y), static_cast<T>(-0.5) * (C.x - Cp.x)};
             }
@@ -212,14 +214,15 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
             const PlaneRef r = plane_ref(args, p);
             const cx<T> *Wz = W_of(r);
             const cx<T> *Wnz = Wn_of(r);
-            const uint32_t even_off = static_cast<uint32_t>((2 * yt * n + yc) * CSZ);
+            const uint32_t rs = rs_of(r);
+            const uint32_t even_off = static_cast<uint32_t>(2 * yt) * rs + yc * CSZ;
 #pragma unroll
             for (int q = 0; q < NWV; ++q) {  // clamped, so every thread loads (no divergent definition)
                 const int i = tid + q * BLK;
                 nw[q] = Wnz[i < 2 * n ? i : 2 * n - 1];
             }
 #pragma unroll
-            for (int m = 0; m < E; ++m) e[m] = at<T>(Wz, even_off + m * 2 * NB * n * CSZ);
+            for (int m = 0; m < E; ++m) e[m] = at<T>(Wz, even_off + m * 2 * NB * rs);
         };
         auto stage_nyquist = [&]() {
 #pragma unroll
@@ -233,12 +236,13 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
         __syncthreads();  // twiddles and the first Nyquist column visible
         for (;;) {
             lanes();
-            const uint32_t even_off = static_cast<uint32_t>((2 * yt * n + yc) * CSZ);
             const PlaneRef r = plane_ref(args, pl);
+            const uint32_t rs = rs_of(r);
+            const uint32_t even_off = static_cast<uint32_t>(2 * yt) * rs + yc * CSZ;
             const cx<T> *Wz = W_of(r);
             cx<T> o[E];  // odd rows, in flight while the even ones are transformed
 #pragma unroll
-            for (int m = 0; m < E; ++m) o[m] = at<T>(Wz, even_off + (m * 2 * NB + 1) * n * CSZ);
+            for (int m = 0; m < E; ++m) o[m] = at<T>(Wz, even_off + (m * 2 * NB + 1) * rs);
             // the barrier before the loop or at the end of the previous plane
             // published the Nyquist column and retired the readers of the plane
             {  // y step: column kx = 0 also carries kx = n (as Y0 + i Yn)

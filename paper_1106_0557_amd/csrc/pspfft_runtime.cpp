@@ -271,9 +271,9 @@ void destroy_plan(pspfft_plan_t p) {
 }
 
 // Every device array of a solve (source, potential, workspace, spectrum) is
-// addressable with 31-bit byte offsets.
-bool arrays_below_2gb(pspfft_plan_t p) {
-    const size_t lim = size_t(1) << 31;
+// addressable with unsigned 32-bit byte offsets.
+bool arrays_below_4gb(pspfft_plan_t p) {
+    const size_t lim = size_t(1) << 32;
     const size_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
     const size_t r = real_size(p->prec);
     return ws_bytes(p->n, p->prec) < lim && nx * ny * nz * r < lim && (nz + 1) * (ny + 1) * nx * r < lim;
@@ -378,7 +378,7 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
             const int grid = static_cast<int>((wg + align - 1) / align * align);
             // compile-time geometry when every line has two stages (radices E, K)
             // or three (E, M, K), the workgroup holds the default number of lines,
-            // and every array is below 2 GB (32-bit offsets)
+            // and every array is below 4 GB (32-bit offsets)
             const int M = E & -E;
             int fix = 0;
             if (K > 1) {
@@ -390,7 +390,7 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
                 if (fix == 3 && pspfft::default_tile(prec, false) * cnb > pspfft::max_block_for(prec, E)) fix = 0;
                 for (size_t j = c0; j < c1 && fix; ++j) {
                     const AxisPlan &ax = plans[idx[j]]->host.ax[axis];
-                    if (ax.nst != a0.nst || ax.NB != cnb || !arrays_below_2gb(plans[idx[j]])) fix = 0;
+                    if (ax.nst != a0.nst || ax.NB != cnb || !arrays_below_4gb(plans[idx[j]])) fix = 0;
                 }
             }
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "
@@ -559,12 +559,29 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
         p->host.ax[a].post = a == 0 ? static_cast<char *>(p->tw[a]) + p->host.ax[a].ntw * cs : nullptr;
         bytes += tb;
     }
+    // Workspace z tiles.  Only meshes whose z planes span 4 MB or more are
+    // tiled: there the z lines of the z pass miss the address translation
+    // caches, while for smaller planes the wider row stride costs more than it
+    // saves.  The tile is the largest power of two up to 16 (PSPFFT_ZTILE
+    // overrides the cap) dividing the z lines' threads per line.
+    {
+        const size_t plane = static_cast<size_t>(2) * ny * nx * cs;
+        int cap = plane >= (size_t(4) << 20) ? 16 : 1;
+        if (const char *e = std::getenv("PSPFFT_ZTILE")) {
+            const int v = std::atoi(e);
+            if (v >= 1 && v <= 16 && (v & (v - 1)) == 0) cap = v;
+        }
+        const int nbz = p->host.ax[2].NB;
+        int zb = 1;
+        while (zb < cap && nbz % (2 * zb) == 0) zb *= 2;
+        p->host.zb = zb;
+    }
     // fused x-y plane kernels: nx == ny = E*K (at most two stages) and the plane fits in LDS
     {
         const AxisPlan &ax = p->host.ax[0];
         const int K = ax.nst == 1 ? 1 : ax.R[1];
         p->fused = !(flags & PSPFFT_PLAN_FIVE_PASS) && nx == ny && ax.nst <= 2 && ax.E * K == nx &&
-                   ax.ntw == nx - 1 && pspfft::plane_fits(p->host.prec, ax.E, K);
+                   ax.ntw == nx - 1 && pspfft::plane_fits(p->host.prec, ax.E, K) && p->host.zb == 1;
         if (p->fused) {
             p->pE = ax.E;
             p->pK = K;
@@ -740,6 +757,8 @@ size_t pspfft_pass_bytes(pspfft_plan_t plan, pspfft_pass pass) {
 }
 
 int pspfft_plan_fused(pspfft_plan_t plan) { return plan && plan->fused ? 1 : 0; }
+
+int pspfft_workspace_ztile(pspfft_plan_t plan) { return plan ? plan->host.zb : 0; }
 
 pspfft_status pspfft_plan_info(pspfft_plan_t plan, int dims[3], double h[3], pspfft_precision *prec) {
     if (!plan) return PSPFFT_ERR_INVALID_ARGUMENT;

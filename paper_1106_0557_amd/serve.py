@@ -71,6 +71,12 @@ class GpuExecutor:
         self.pool: Dict[Any, List[Any]] = collections.defaultdict(list)
         # default priority streams only
         self.streams = [torch.cuda.Stream(device=device) for _ in range(NUM_PASSES)]
+        # first work on a stream sets up its queue; do that now rather than
+        # inside the first steps that happen to use it
+        for s in self.streams:
+            with torch.cuda.stream(s):
+                torch.zeros(1, device=f"cuda:{device}")
+            s.synchronize()
         self._last_step_event = None
         self._used = []
         self._events: List[Any] = []  # recycled events

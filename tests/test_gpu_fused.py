@@ -112,7 +112,8 @@ def test_fused_passes_match_oracle_stages(mesh):
     csz = 16
     main = nz * 2 * ny * nx * csz
     off = (main + 255) // 256 * 256
-    W = mem[:main].view(torch.complex128).view(nz, 2 * ny, nx)
+    B = plan.ztile  # W is [nz/B][2ny][B][nx] (pspfft_workspace_ztile)
+    W = mem[:main].view(torch.complex128).view(nz // B, 2 * ny, B, nx).permute(0, 2, 1, 3)
     Wn = mem[off:off + nz * 2 * ny * csz].view(torch.complex128).view(nz, 2 * ny)
     Sd = torch.from_numpy(S).cuda()
     Phi = torch.empty_like(Sd)
@@ -122,7 +123,7 @@ def test_fused_passes_match_oracle_stages(mesh):
     A = oracle.fft_axis(oracle.fft_axis(A, 0), 1)
     pass_batched(PASS_X_FWD, [ws], S=[Sd], Phi=[Phi])
     torch.cuda.synchronize()
-    got, gotn = W.cpu().numpy(), Wn.cpu().numpy()
+    got, gotn = W.reshape(nz, 2 * ny, nx).cpu().numpy(), Wn.cpu().numpy()
     ref = A[:nz, :, : nx + 1]
     scale = np.abs(ref).max()
     e = max(np.abs(got - ref[:, :, :nx]).max(), np.abs(gotn - ref[:, :, nx]).max()) / scale
