@@ -80,6 +80,7 @@ class GpuExecutor:
         self._last_step_event = None
         self._used = []
         self._events: List[Any] = []  # recycled events
+        self._ws_bytes: Dict[Any, int] = {}  # workspace bytes per mesh
 
     # ------------------------------------------------------------- plans
     def key(self, req: Request):
@@ -95,8 +96,12 @@ class GpuExecutor:
         return p
 
     def workspace_bytes(self, req: Request) -> int:
-        nx, ny, nz = req.n
-        return self.ps.workspace_bytes(nx, ny, nz, self.dtype)
+        k = req.n
+        b = self._ws_bytes.get(k)
+        if b is None:
+            nx, ny, nz = k
+            b = self._ws_bytes[k] = self.ps.workspace_bytes(nx, ny, nz, self.dtype)
+        return b
 
     def active_passes(self, req: Request) -> Tuple[int, ...]:
         return self.plan(req).active_passes
@@ -112,10 +117,12 @@ class GpuExecutor:
     def acquire(self, req: Request):
         k = self.key(req)
         if self.pool[k]:
-            ws = self.pool[k].pop()
-        else:
-            ws = self.plan(req).workspace()
-        return ws
+            return self.pool[k].pop()
+        # memory from torch's caching allocator, wrapped as a workspace: creating
+        # and trimming pooled workspaces then costs no device allocation calls
+        plan = self.plan(req)
+        mem = self.torch.empty(plan.workspace_bytes, dtype=self.torch.uint8, device=f"cuda:{self.device}")
+        return self.ps.Workspace(plan, memory=mem)
 
     def release(self, req: Request, ws) -> None:
         self.pool[self.key(req)].append(ws)
@@ -401,9 +408,9 @@ def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, 
                 out.append(Request(i, (nn, nn, nn), (1.0 / nn,) * 3, S, arrival=t))
             return out
 
-        # warm plans and kernels
+        # warm plans, kernels and the workspace pool (a server does this at start-up)
         warm = Server(ex, budget, max_inflight=max_inflight)
-        warm.run_trace(make([(0.0, s) for s in szs for _ in range(2)]), realtime=False)
+        warm.run_trace(make([(0.0, s) for _ in range(4 * max_inflight) for s in szs]), realtime=False)
         ex.synchronize()
         # closed loop: all requests present at t = 0
         trace = sources.config4_trace(rate_hz=0, count=count, sizes=szs, weights=wts)
