@@ -214,7 +214,7 @@ class Server:
     device, ``max_steps_ahead`` the scheduler steps enqueued but not finished.
     """
 
-    def __init__(self, executor, budget_bytes: int, max_inflight: int = 64, max_steps_ahead: int = 4,
+    def __init__(self, executor, budget_bytes: int, max_inflight: int = 64, max_steps_ahead: int = 16,
                  clock: Callable[[], float] = time.perf_counter):
         self.ex = executor
         self.budget = int(budget_bytes)

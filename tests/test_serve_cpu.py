@@ -183,7 +183,7 @@ def test_requests_join_while_others_are_in_flight():
 
 def test_pool_reuse_and_trim():
     ex = FakeExecutor()
-    srv = Server(ex, budget_bytes=1 << 40, max_inflight=2)
+    srv = Server(ex, budget_bytes=1 << 40, max_inflight=2, max_steps_ahead=2)
     srv.run_trace(_reqs([16] * 6), realtime=False)
     # two slots; a finished request keeps its workspace until its step's token
     # completes, so at most slots x (1 + steps ahead) exist, and they are reused
