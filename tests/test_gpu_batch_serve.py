@@ -105,15 +105,18 @@ def test_served_results_equal_alone_in_the_mix():
     import paper_1106_0557_amd as ps
     from paper_1106_0557_amd.serve import Request
 
-    say("[serve] mixed sizes, results alone vs in the mix")
+    say("[serve] mixed sizes (fused and five-pass plans), results alone vs in the mix")
     rng = np.random.default_rng(41)
-    sizes = [int(rng.choice([32, 48, 64, 96])) for _ in range(40)]
+    sizes = [int(rng.choice([32, 48, 64, 96, 144])) for _ in range(40)]
     reqs = []
     for i, n in enumerate(sizes):
         S = sources.blob_field(n, sources.draw_blobs(rng, 8), device="cuda").to(torch.float32)
         reqs.append(Request(i, (n, n, n), (1.0 / n,) * 3, S))
     ex, srv, fin = _serve(reqs, budget=1 << 34, max_inflight=7)
     assert len(fin) == len(reqs) and all(r.done and not r.rejected for r in fin)
+    fused = {n: ex.plans[ex.key(r)].fused for r in fin for n in [r.n[0]]}
+    say(f"  fused plans by size: {fused}")
+    assert fused[144] is False and fused[64] is True
     say(f"  {srv.launches} launches, max group {srv.max_batch}")
     for r in fin:
         alone = ex.plans[ex.key(r)].solve(r.S)

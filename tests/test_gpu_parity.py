@@ -80,17 +80,25 @@ def _workspace_views(plan, mem):
     return (lambda: Wt.permute(0, 2, 1, 3).reshape(nz, 2 * ny, nx)), Wn
 
 
-@pytest.mark.parametrize("n", [(24, 20, 16), (16, 36, 24), (40, 16, 18)])
-def test_each_pass_matches_oracle_stage(n):
-    """Run the passes one at a time and compare the workspace with the oracle's stages."""
+@pytest.mark.parametrize("n,ztile", [((24, 20, 16), None), ((16, 36, 24), None), ((40, 16, 18), None),
+                                     ((24, 20, 32), "4"), ((16, 12, 128), "16")])
+def test_each_pass_matches_oracle_stage(n, ztile, monkeypatch):
+    """Run the passes one at a time and compare the workspace with the oracle's stages.
+
+    With ``ztile`` the workspace is forced into tiles of z planes (PSPFFT_ZTILE),
+    which large meshes get by themselves, and read back through the documented layout."""
+    if ztile is not None:
+        monkeypatch.setenv("PSPFFT_ZTILE", ztile)
     from paper_1106_0557_amd import (PASS_X_FWD, PASS_Y_FWD, PASS_Z_CONV, PASS_Y_INV, PASS_X_INV, Plan,
                                      Workspace, pass_batched)
 
-    say(f"[passes] n={n}")
+    say(f"[passes] n={n} ztile={ztile}")
     nx, ny, nz = n
     h = (0.3, 0.2, 0.5)
     S = sources.random_field(n, seed=11).numpy()
     plan = Plan(*n, h=h, dtype=torch.float64)
+    if ztile is not None:
+        assert plan.ztile == int(ztile), plan.ztile
     mem = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     ws = Workspace(plan, memory=mem)
     W, Wn = _workspace_views(plan, mem)
