@@ -179,10 +179,9 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                     if (yc == 0) {
 #pragma unroll
                         for (int m = 0; m < E; ++m) sep[2 * (yt + NB * m) + parity] = q[m];
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < E; ++m) at<T>(Wz, wy_off + (m * 2 * NB + parity) * rs) = q[m];
                     }
+#pragma unroll
+                    for (int m = 0; m < E; ++m) at<T>(Wz, wy_off + (m * 2 * NB + parity) * rs) = q[m];
                 };
                 ColF::template run<K>(v, ax, lds, SP, twl, cp, yt);  // Y[2j]
                 emit(v, 0);
