@@ -125,6 +125,18 @@ __host__ __device__ constexpr int default_tile(int prec, bool row) {
     return row ? (prec == 0 ? 32 : 16) : (prec == 0 ? 16 : 8);
 }
 
+#ifndef PSPFFT_COL_BLOCK_CAP
+#define PSPFFT_COL_BLOCK_CAP 1024
+#endif
+// Lines per workgroup for lines of nb threads: the default tile, except that
+// column workgroups stay at or below PSPFFT_COL_BLOCK_CAP threads.
+__host__ __device__ constexpr int fix_tile(int prec, bool row, int nb) {
+    int t = default_tile(prec, row);
+    if (!row && nb > 0)
+        while (t > 1 && t * nb > PSPFFT_COL_BLOCK_CAP) t /= 2;
+    return t;
+}
+
 __host__ __device__ constexpr int max_block_for(int prec, int E) {
     return prec == 0 ? (E == 16 ? 1024 : (E <= 24 ? 512 : 256)) : (E == 16 ? 512 : 256);
 }

@@ -248,8 +248,8 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr bool ROW = (MODE == X_FWD || MODE == X_INV);
     constexpr int H = E / 2;  // registers m < H hold the first half of the line
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
-    constexpr int FTILE = default_tile(sizeof(T) == 4 ? 0 : 1, ROW);
     constexpr int CNB = FIX == 2 ? K : (FIX == 3 ? (E & -E) * K : 0);
+    constexpr int FTILE = fix_tile(sizeof(T) == 4 ? 0 : 1, ROW, CNB);
     constexpr int CL = E * CNB;  // line length when compile-time
     constexpr int CLDSW = FIX ? (ROW ? row_stride(CL, CNB, CSZ) : FTILE + 1) : 0;
     using FFT_F = LineFFT<T, E, -1, ROW, CNB, CLDSW>;
@@ -513,6 +513,224 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     }
 }
 
+// ------------------------------------------------ persistent z convolution --
+// Store of one complex value through a raw buffer resource: a store at or past
+// `bytes` is dropped by the hardware's range check, so lanes without a line
+// store nothing without a branch around the store.
+template <typename T>
+__device__ __forceinline__ void buffer_store(const cx<T> v, char *base, uint32_t bytes, uint32_t off) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, static_cast<short>(0),
+                                                                        static_cast<int>(bytes), 0x00020000);
+    if constexpr (sizeof(T) == 4) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, 0);
+    } else {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rs, off, 0, 0);
+    }
+}
+
+// One z line of a compile-time Z_CONV launch for lane (c, t) of the tile that
+// virtual workgroup `bid` handles: the same decomposition as pass_kernel's.
+template <typename T>
+struct ZLine {
+    LinePtr<T, true> lane;  // positions t + NB*m of the line in W (or Wn)
+    const gbl<const char> *g;  // spectrum octant (G, or Gn for the Nyquist column)
+    uint32_t glo, ghi, gstep;  // byte offsets of positions t + NB*m (m < E/2) and NB*(E-m) - t
+    uint32_t bytes;            // size of the line's array (W or Wn)
+    int active;
+};
+
+template <typename T, int E, int NB, int TILE>
+__device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int c, int t) {
+    constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
+    int sgi = 0;
+    while (sgi + 1 < args.nseg && bid >= args.seg[sgi + 1].wg_begin) ++sgi;
+    const Segment &sg = args.seg[sgi];
+    int local = bid - sg.wg_begin;
+    const int member = local % sg.group;
+    local /= sg.group;
+    const ProbArg &pa = args.p[sg.first + member];
+    // The plan is read through the constant address space: it does not change
+    // during the launch, so its fields come in scalar loads even after the
+    // stores of an earlier tile (a vector load there would wait for them).
+    using cplan = const __attribute__((address_space(4))) DevPlan;
+    const auto &pl = *(cplan *)pa.plan;
+    const int nx = pl.nx, ny = pl.ny;
+    const bool nyq = local >= sg.wg_main;
+    if (nyq) local -= sg.wg_main;
+    const int g = local * TILE + c;
+    ZLine<T> zl;
+    int ky, kx;
+    size_t lane_off;
+    const void *arr;
+    if (!nyq) {
+        // rows of the plane in the order 0, 1, 2ny-1, 2, 2ny-2, ..., ny: ky and its
+        // mirror (same spectrum values) go to neighbouring tiles
+        zl.active = g < 2 * ny * nx;
+        const int vrow = zl.active ? g / nx : 0;
+        kx = g - vrow * nx;
+        ky = vrow == 0 ? 0 : (vrow == 2 * ny - 1 ? ny : ((vrow & 1) ? (vrow + 1) >> 1 : 2 * ny - (vrow >> 1)));
+        arr = pa.W;
+        // z = t + NB*m sits in tile z/zb at row z%zb; zb divides NB
+        const int zb = pl.zb;
+        const int sh = __builtin_ctz(static_cast<unsigned>(zb));
+        lane_off = static_cast<size_t>(ky) * zb * nx + kx +
+                   (static_cast<size_t>(t >> sh) * 2 * ny * zb + (t & (zb - 1))) * nx;
+        zl.lane = line_ptr<T, true>(arr, zl.active ? lane_off : 0, static_cast<size_t>(NB) * 2 * ny * nx, CSZ);
+        zl.bytes = static_cast<uint32_t>(static_cast<size_t>(pl.nz) * 2 * ny * nx * CSZ);
+    } else {
+        zl.active = g < 2 * ny;
+        ky = g;
+        kx = nx;
+        arr = pa.Wn;
+        lane_off = static_cast<size_t>(g) + static_cast<size_t>(t) * 2 * ny;
+        zl.lane = line_ptr<T, true>(arr, zl.active ? lane_off : 0, static_cast<size_t>(NB) * 2 * ny, CSZ);
+        zl.bytes = static_cast<uint32_t>(static_cast<size_t>(pl.nz) * 2 * ny * CSZ);
+    }
+    // G~ is even in ky and kz: octant index min(k, 2n - k)
+    const int kyo = ky <= ny ? ky : 2 * ny - ky;
+    zl.g = as_global(static_cast<const char *>(nyq ? pl.Gn : pl.G));
+    const size_t gb = nyq ? static_cast<size_t>(kyo) : static_cast<size_t>(kyo) * nx + kx;
+    const size_t gs = nyq ? static_cast<size_t>(ny + 1) : static_cast<size_t>(ny + 1) * nx;
+    zl.glo = zl.active ? static_cast<uint32_t>((gb + t * gs) * sizeof(T)) : 0u;
+    zl.ghi = zl.active ? static_cast<uint32_t>((gb + (NB - t) * gs) * sizeof(T)) : 0u;
+    zl.gstep = static_cast<uint32_t>(static_cast<size_t>(NB) * gs * sizeof(T));
+    return zl;
+}
+
+// Z_CONV with compile-time geometry, persistent: workgroup b handles the tiles
+// b, b + gridDim.x, ...  The stored half of the next tile's line and its
+// spectrum values are loaded before the current tile's stores.  Vector loads and
+// stores retire in order, so waiting for those values never waits for the
+// stores, and the loads run under the current tile's transforms.  Every problem
+// of such a launch has the same line length and radices, hence the same stage
+// twiddles, which are staged once.
+template <typename T, int E, int K, int FIX>
+__global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zconv_kernel(const LaunchArgs args) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
+    constexpr int H = E / 2;
+    constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
+    constexpr int NB = FIX == 2 ? K : (E & -E) * K;
+    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, false, NB);
+    constexpr int LDSW = TILE + 1;
+    using FFT_F = LineFFT<T, E, -1, false, NB, LDSW>;
+    using FFT_I = LineFFT<T, E, +1, false, NB, LDSW>;
+    static_assert(FIX == 2 || FIX == 3, "compile-time geometry only");
+
+    int bid = static_cast<int>(blockIdx.x);
+    if (bid >= args.nwg) return;
+    const int tid = threadIdx.x;
+    const int c = tid & (TILE - 1);
+    const int t = tid >> __builtin_ctz(TILE);
+    const AxisPlan &ax0 = args.p[0].plan->ax[2];
+    cx<T> *twl = lds + data_elems(false, E * NB, NB, TILE * NB, CSZ);
+    copy_to_lds<T>(twl, ax0.tw, ax0.ntw);  // visible after the first transform's leading barrier
+
+    // Spectrum values of a line: G~ is even in kz, so position t + NB*m reads
+    // octant index t + NB*m for m < E/2 and NB*(E - m) - t otherwise.
+    auto load_g = [](const ZLine<T> &zl, T *gv) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const uint32_t idx = m < H ? m : E - m - 1;
+            gv[m] = *reinterpret_cast<const gbl<T> *>(zl.g + ((m < H ? zl.glo : zl.ghi) + idx * zl.gstep));
+        }
+    };
+    ZLine<T> cur = z_line<T, E, NB, TILE>(args, bid, c, t);
+    cx<T> nxt[H];
+    T gnx[E];
+#pragma unroll
+    for (int m = 0; m < H; ++m) nxt[m] = cur.lane[m];
+    load_g(cur, gnx);
+    // Nothing outstanding when the loop is entered, as at the end of each pass
+    // through it (vmcnt 0, expcnt and lgkmcnt unconstrained).
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    for (;;) {
+        cx<T> v[E];
+        T gv[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            v[m] = m < H ? nxt[m] : cx<T>{T(0), T(0)};
+            gv[m] = gnx[m];
+        }
+        // The next tile's line and spectrum values are loaded before this tile's
+        // stores, and unconditionally (the last tile loads its own again; lanes
+        // without a line store out of range), so the compiler counts the same
+        // outstanding operations on every path and no wait covers the stores.
+        const int nbid = bid + static_cast<int>(gridDim.x);
+        const bool more = nbid < args.nwg;
+        const ZLine<T> fol = z_line<T, E, NB, TILE>(args, more ? nbid : bid, c, t);
+#pragma unroll
+        for (int m = 0; m < H; ++m) nxt[m] = fol.lane[m];
+        load_g(fol, gnx);
+        FFT_F::template run<K>(v, ax0, lds, LDSW, twl, c, t);
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = scale(v[m], gv[m]);
+        FFT_I::template run<K>(v, ax0, lds, LDSW, twl, c, t);
+        // the out-of-range offset is chosen per element (a sum could wrap into range)
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const uint32_t off = static_cast<uint32_t>(cur.lane.lane) +
+                                 static_cast<uint32_t>(m) * static_cast<uint32_t>(cur.lane.step);
+            buffer_store<T>(v[m], cur.lane.base, cur.bytes, cur.active ? off : 0xfffffff0u);
+        }
+        if (!more) break;
+        cur = fol;
+        bid = nbid;
+    }
+}
+
+// Where the persistent z convolution runs (PSPFFT_ZCONV_PERSIST: 0 never, 1
+// always, unset: where one workgroup fills a compute unit).  With two or more
+// workgroups per unit the hardware already overlaps one's memory traffic with
+// another's transforms, and its in-order dispatch keeps the tiles in flight
+// neighbours in memory, which long-lived workgroups drift away from.
+inline int zconv_persist_mode() {
+    static int v = -2;
+    if (v == -2) {
+        v = -1;
+        if (const char *e = std::getenv("PSPFFT_ZCONV_PERSIST")) v = std::atoi(e) != 0 ? 1 : 0;
+    }
+    return v;
+}
+
+// Launches the persistent z convolution and returns true where it is chosen;
+// *err receives the launch status.  The grid is what the device holds at once.
+template <typename T, int E, int K, int FIX>
+bool launch_zconv(const LaunchArgs &args, int block, size_t lds, hipStream_t stream, hipError_t *err) {
+    constexpr int kMaxDevices = 64;
+    static int per_cu[kMaxDevices] = {0}, cus[kMaxDevices] = {0};
+    auto fn = zconv_kernel<T, E, K, FIX>;
+    const int mode = zconv_persist_mode();
+    if (mode == 0) return false;
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return true;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return true;
+    }
+    if (per_cu[dev] == 0) {
+        *err = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024);
+        if (*err != hipSuccess) return true;
+        int p = 0, c = 0;
+        *err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, fn, block, lds);
+        if (*err != hipSuccess) return true;
+        *err = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (*err != hipSuccess) return true;
+        per_cu[dev] = p > 0 ? p : 1;
+        cus[dev] = c > 0 ? c : 1;
+    }
+    if (mode < 0 && per_cu[dev] > 1) return false;
+    int grid = per_cu[dev] * cus[dev];
+    if (grid > args.nwg) grid = args.nwg;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, stream, args);
+    *err = hipGetLastError();
+    return true;
+}
+
 template <typename T, int E, int K, int MODE, int FIX>
 hipError_t launch_kernel(const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
     static bool attr_set = false;
@@ -532,7 +750,12 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
     switch (mode) {
         case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
         case Y_FWD: return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
-        case Z_CONV: return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
+        case Z_CONV:
+            if constexpr (FIX != 0) {
+                hipError_t e = hipSuccess;
+                if (launch_zconv<T, E, K, FIX>(args, block, lds, stream, &e)) return e;
+            }
+            return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
         case Y_INV: return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
         case X_INV: return launch_kernel<T, E, K, X_INV, FIX>(args, grid, block, lds, stream);
         default: return hipErrorInvalidValue;
@@ -549,7 +772,7 @@ hipError_t launch_fix(int mode, int fix, const LaunchArgs &args, int grid, int b
     constexpr int M = E & -E;
     if constexpr (K > 1) {
         if (fix == 2) return launch_mode<T, E, K, 2>(mode, args, grid, block, lds, stream);
-        if constexpr (default_tile(prec, false) * M * K <= max_block_for(prec, E)) {
+        if constexpr (fix_tile(prec, false, M * K) * M * K <= max_block_for(prec, E)) {
             if (fix == 3) return launch_mode<T, E, K, 3>(mode, args, grid, block, lds, stream);
         }
     }

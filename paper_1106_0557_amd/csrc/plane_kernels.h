@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
 }
 
 // Planes one workgroup of a plane kernel takes at most (PSPFFT_PLANES_PER_WG,
-// default 8); the grid never goes below what the device holds at once.
+// default 8).
 inline int planes_per_workgroup() {
     static int v = 0;
     if (v == 0) {
@@ -319,9 +319,9 @@ inline int planes_per_workgroup() {
     return v;
 }
 
-// Grid: as many workgroups as the device holds at once (from the occupancy of
-// this kernel), or more when that would give a workgroup more planes than
-// planes_per_workgroup(); never more than one per plane.
+// Grid: a whole number of generations of what the device holds at once (from
+// the occupancy of this kernel), as few as keep every workgroup at or below
+// planes_per_workgroup() planes; never more than one per plane.
 template <typename T, int E, int K, bool FWD>
 hipError_t launch_plane_kernel(const LaunchArgs &args, size_t lds, hipStream_t stream) {
     constexpr int kMaxDevices = 64;
@@ -344,9 +344,13 @@ hipError_t launch_plane_kernel(const LaunchArgs &args, size_t lds, hipStream_t s
     }
     // at most planes_per_workgroup() planes each: more workgroups than the device
     // holds at once leave room for kernels on other streams
+    // whole generations of resident workgroups, each taking at most `per` planes:
+    // workgroups then differ by at most one plane, and no short last generation
+    // runs alone at the end
     const int per = planes_per_workgroup();
-    const int want = (args.nwg + per - 1) / per;
-    int grid = want > resident[dev] ? want : resident[dev];
+    const long gens = (static_cast<long>(args.nwg) + static_cast<long>(resident[dev]) * per - 1) /
+                      (static_cast<long>(resident[dev]) * per);
+    int grid = static_cast<int>(gens * resident[dev]);
     if (grid > args.nwg) grid = args.nwg;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(E * K * K), lds, stream, args);
     return hipGetLastError();

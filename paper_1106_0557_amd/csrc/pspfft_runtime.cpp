@@ -313,17 +313,14 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
         });
         // Column passes: 128-byte rows of complex values per wavefront row.
         // Row passes: enough rows per workgroup for 256-thread groups.
-        const int tile_target = line_tile(mode, pspfft::default_tile(prec, row));
         const int bmax = pspfft::max_block_for(prec, E);
         const int csz = prec == 0 ? 8 : 16;
         for (size_t c0 = 0; c0 < idx.size(); c0 += pspfft::kMaxProblems) {
             const size_t c1 = std::min(idx.size(), c0 + pspfft::kMaxProblems);
             int block = 0, nbmax = 1;
-            for (size_t j = c0; j < c1; ++j) {
-                const int NB = plans[idx[j]]->host.ax[axis].NB;
-                nbmax = std::max(nbmax, NB);
-                block = std::max(block, tile_target * NB);
-            }
+            for (size_t j = c0; j < c1; ++j) nbmax = std::max(nbmax, plans[idx[j]]->host.ax[axis].NB);
+            const int tile_target = line_tile(mode, pspfft::fix_tile(prec, row, nbmax));
+            for (size_t j = c0; j < c1; ++j) block = std::max(block, tile_target * plans[idx[j]]->host.ax[axis].NB);
             block = std::min(std::max(block, 64), bmax);
             auto lds_need = [&](int blk) {
                 size_t need = 0;
@@ -386,8 +383,8 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
                 if (a0.nst == 2) fix = 2;
                 else if (a0.nst == 3 && a0.R[1] == M) fix = 3;
                 const int cnb = fix == 2 ? K : M * K;
-                if (fix && block != pspfft::default_tile(prec, row) * cnb) fix = 0;
-                if (fix == 3 && pspfft::default_tile(prec, false) * cnb > pspfft::max_block_for(prec, E)) fix = 0;
+                if (fix && block != pspfft::fix_tile(prec, row, cnb) * cnb) fix = 0;
+                if (fix == 3 && pspfft::fix_tile(prec, false, cnb) * cnb > pspfft::max_block_for(prec, E)) fix = 0;
                 for (size_t j = c0; j < c1 && fix; ++j) {
                     const AxisPlan &ax = plans[idx[j]]->host.ax[axis];
                     if (ax.nst != a0.nst || ax.NB != cnb || !arrays_below_4gb(plans[idx[j]])) fix = 0;
