@@ -121,6 +121,15 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
 int pspfft_plan_fused(pspfft_plan_t plan);
 
 /*
+ * 1 if the plan keeps its spectrum kz-fastest, 0 otherwise (and for NULL).
+ * That is the case where the z lines have three stages with 64 threads per line
+ * (2 nz = 16 * 16 * 4, nz = 512) and every array of a solve is below 4 GB: the
+ * z pass then gives each line to one wavefront, which reads its spectrum values
+ * in contiguous runs.  pspfft_plan_green exports the same octant either way.
+ */
+int pspfft_plan_spectrum_kz_fastest(pspfft_plan_t plan);
+
+/*
  * Workspace layout, for code that reads a workspace between passes (tests,
  * debugging).  A workspace of this plan holds, in the plan's complex type,
  *   W  = [nz / B][2 ny][B][nx]  then, 256-byte aligned,  Wn = [nz][2 ny],

@@ -69,6 +69,7 @@ class Plan:
         self._handle = handle.value
         self._lib = lib
         self.fused = bool(lib.pspfft_plan_fused(self._handle))
+        self.spectrum_kz_fastest = bool(lib.pspfft_plan_spectrum_kz_fastest(self._handle))
         self.ztile = int(lib.pspfft_workspace_ztile(self._handle))  # z planes per workspace tile
         # passes that launch work for this plan (a fused plan skips the y passes)
         self.active_passes = tuple(p for p in range(5) if lib.pspfft_pass_bytes(self._handle, p) > 0)

@@ -32,7 +32,8 @@ PASS_NAMES = ("x_fwd", "y_fwd", "z_conv", "y_inv", "x_inv")
 
 # Every symbol the header declares, for the load check.
 EXPORTS = (
-    "pspfft_plan_create", "pspfft_plan_create_ex", "pspfft_plan_fused", "pspfft_workspace_ztile",
+    "pspfft_plan_create", "pspfft_plan_create_ex", "pspfft_plan_fused", "pspfft_plan_spectrum_kz_fastest",
+    "pspfft_workspace_ztile",
     "pspfft_destroy", "pspfft_solve",
     "pspfft_workspace_create", "pspfft_workspace_wrap", "pspfft_workspace_destroy",
     "pspfft_solve_ws", "pspfft_solve_batched", "pspfft_pass_batched",
@@ -74,6 +75,7 @@ def load():
         "pspfft_plan_create": ([ip, ip, ip, dp, ip, vpp], ip),
         "pspfft_plan_create_ex": ([ip, ip, ip, dp, ip, ctypes.c_uint, vpp], ip),
         "pspfft_plan_fused": ([vp], ip),
+        "pspfft_plan_spectrum_kz_fastest": ([vp], ip),
         "pspfft_workspace_ztile": ([vp], ip),
         "pspfft_destroy": ([vp], ip),
         "pspfft_solve": ([vp, vp, vp, vp], ip),

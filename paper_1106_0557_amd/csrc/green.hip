@@ -99,26 +99,37 @@ __global__ void green_axis(const double *in, double *out, int A, int M, int B, i
     }
 }
 
-template <typename T>
-__global__ void green_store(const double *a, int nx, int ny, int nz, double s, T *G, T *Gn) {
-    const long total = static_cast<long>(nx + 1) * (ny + 1) * (nz + 1);
-    const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= total) return;
+// Position in G (kx < nx) or Gn (kx == nx) of octant element (kx, ky, kz) whose
+// dense index is i = (kz*(ny+1) + ky)*(nx+1) + kx.
+__device__ __forceinline__ long green_pos(long i, int nx, int ny, int nz, int gz, bool &nyq) {
     const long kx = i % (nx + 1);
-    const long row = i / (nx + 1);
-    const T v = static_cast<T>(a[i] * s);
-    if (kx < nx) G[row * nx + kx] = v;
-    else Gn[row] = v;
+    const long row = i / (nx + 1);  // kz*(ny+1) + ky
+    nyq = kx == nx;
+    if (!gz) return nyq ? row : row * nx + kx;
+    const long kz = row / (ny + 1), ky = row - kz * (ny + 1);
+    return nyq ? ky * (nz + 1) + kz : (ky * nx + kx) * (nz + 1) + kz;
 }
 
 template <typename T>
-__global__ void green_load(const T *G, const T *Gn, int nx, int ny, int nz, T *dst) {
+__global__ void green_store(const double *a, int nx, int ny, int nz, int gz, double s, T *G, T *Gn) {
     const long total = static_cast<long>(nx + 1) * (ny + 1) * (nz + 1);
     const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    const long kx = i % (nx + 1);
-    const long row = i / (nx + 1);
-    dst[i] = kx < nx ? G[row * nx + kx] : Gn[row];
+    bool nyq;
+    const long q = green_pos(i, nx, ny, nz, gz, nyq);
+    const T v = static_cast<T>(a[i] * s);
+    if (nyq) Gn[q] = v;
+    else G[q] = v;
+}
+
+template <typename T>
+__global__ void green_load(const T *G, const T *Gn, int nx, int ny, int nz, int gz, T *dst) {
+    const long total = static_cast<long>(nx + 1) * (ny + 1) * (nz + 1);
+    const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    bool nyq;
+    const long q = green_pos(i, nx, ny, nz, gz, nyq);
+    dst[i] = nyq ? Gn[q] : G[q];
 }
 
 static hipError_t axis_pass(const double *in, double *out, int A, int M, int B, const double *cos_tab,
@@ -140,7 +151,7 @@ static hipError_t axis_pass(const double *in, double *out, int A, int M, int B, 
     return hipGetLastError();
 }
 
-hipError_t green_spectrum(int nx, int ny, int nz, const double h[3], int prec, double *a, double *b,
+hipError_t green_spectrum(int nx, int ny, int nz, const double h[3], int prec, int gz, double *a, double *b,
                           const double *cos_x, const double *cos_y, const double *cos_z, void *G, void *Gn,
                           hipStream_t stream) {
     const long total = static_cast<long>(nx + 1) * (ny + 1) * (nz + 1);
@@ -156,24 +167,24 @@ hipError_t green_spectrum(int nx, int ny, int nz, const double h[3], int prec, d
     if ((e = axis_pass(a, b, 1, nz + 1, (nx + 1) * (ny + 1), cos_z, stream)) != hipSuccess) return e;
     const double s = 1.0 / (8.0 * nx * static_cast<double>(ny) * nz);
     if (prec == 0)
-        hipLaunchKernelGGL(green_store<float>, dim3(nb), dim3(256), 0, stream, b, nx, ny, nz, s,
+        hipLaunchKernelGGL(green_store<float>, dim3(nb), dim3(256), 0, stream, b, nx, ny, nz, gz, s,
                            static_cast<float *>(G), static_cast<float *>(Gn));
     else
-        hipLaunchKernelGGL(green_store<double>, dim3(nb), dim3(256), 0, stream, b, nx, ny, nz, s,
+        hipLaunchKernelGGL(green_store<double>, dim3(nb), dim3(256), 0, stream, b, nx, ny, nz, gz, s,
                            static_cast<double *>(G), static_cast<double *>(Gn));
     return hipGetLastError();
 }
 
-hipError_t green_export(int nx, int ny, int nz, int prec, const void *G, const void *Gn, void *dst,
+hipError_t green_export(int nx, int ny, int nz, int prec, int gz, const void *G, const void *Gn, void *dst,
                         hipStream_t stream) {
     const long total = static_cast<long>(nx + 1) * (ny + 1) * (nz + 1);
     const unsigned nb = static_cast<unsigned>((total + 255) / 256);
     if (prec == 0)
         hipLaunchKernelGGL(green_load<float>, dim3(nb), dim3(256), 0, stream, static_cast<const float *>(G),
-                           static_cast<const float *>(Gn), nx, ny, nz, static_cast<float *>(dst));
+                           static_cast<const float *>(Gn), nx, ny, nz, gz, static_cast<float *>(dst));
     else
         hipLaunchKernelGGL(green_load<double>, dim3(nb), dim3(256), 0, stream, static_cast<const double *>(G),
-                           static_cast<const double *>(Gn), nx, ny, nz, static_cast<double *>(dst));
+                           static_cast<const double *>(Gn), nx, ny, nz, gz, static_cast<double *>(dst));
     return hipGetLastError();
 }
 

@@ -56,6 +56,7 @@ struct AxisPlan {
 struct DevPlan {
     int nx, ny, nz, prec;  // prec: 0 = FP32, 1 = FP64
     int zb;                // z planes per tile of the workspace
+    int gz;                // spectrum kz-fastest (z pass by wavefront-owned lines)
     AxisPlan ax[3];        // x, y, z
     const void *G;         // spectrum, main part
     const void *Gn;        // spectrum, kx = nx
@@ -110,6 +111,11 @@ __host__ __device__ constexpr int row_stride(int L, int NB, int csz) {
     }
     return S;
 }
+// Row stride (complex values) of a line in the wavefront-owned z convolution:
+// the row layout's P + P/16, plus one so that the rows of neighbouring lines
+// start on different banks (the tile is transposed through these rows).
+__host__ __device__ constexpr int wave_line_stride(int L) { return L + L / 16 + 1; }
+
 __host__ __device__ constexpr int data_elems(bool row, int L, int NB, int block, int csz) {
     const int tile = block / NB;
     return row ? tile * row_stride(L, NB, csz) : L * (tile + 1);
@@ -125,15 +131,16 @@ __host__ __device__ constexpr int default_tile(int prec, bool row) {
     return row ? (prec == 0 ? 32 : 16) : (prec == 0 ? 16 : 8);
 }
 
-#ifndef PSPFFT_COL_BLOCK_CAP
-#define PSPFFT_COL_BLOCK_CAP 1024
+#ifndef PSPFFT_ZCONV_BLOCK_CAP
+#define PSPFFT_ZCONV_BLOCK_CAP 1024
 #endif
-// Lines per workgroup for lines of nb threads: the default tile, except that
-// column workgroups stay at or below PSPFFT_COL_BLOCK_CAP threads.
-__host__ __device__ constexpr int fix_tile(int prec, bool row, int nb) {
-    int t = default_tile(prec, row);
-    if (!row && nb > 0)
-        while (t > 1 && t * nb > PSPFFT_COL_BLOCK_CAP) t /= 2;
+// Lines per workgroup of pass `mode` for lines of nb threads: the default tile,
+// except that z convolution workgroups stay at or below PSPFFT_ZCONV_BLOCK_CAP
+// threads.
+__host__ __device__ constexpr int fix_tile(int prec, int mode, int nb) {
+    int t = default_tile(prec, mode == X_FWD || mode == X_INV);
+    if (mode == Z_CONV && nb > 0)
+        while (t > 1 && t * nb > PSPFFT_ZCONV_BLOCK_CAP) t /= 2;
     return t;
 }
 
@@ -208,12 +215,15 @@ inline hipError_t launch_plane(bool fwd, int prec, int E, int K, const LaunchArg
 // Green's-function spectrum in FP64: fills the octant (nz+1)(ny+1)(nx+1) of G
 // into `a`, applies the even-extension cosine transform along each axis (using
 // `b` as scratch) and writes the scaled result in plan precision into G / Gn.
-hipError_t green_spectrum(int nx, int ny, int nz, const double h[3], int prec, double *a, double *b,
+// gz: store kz-fastest, G at (ky*nx + kx)*(nz+1) + kz and Gn at ky*(nz+1) + kz,
+// instead of G at (kz*(ny+1) + ky)*nx + kx and Gn at kz*(ny+1) + ky.
+hipError_t green_spectrum(int nx, int ny, int nz, const double h[3], int prec, int gz, double *a, double *b,
                           const double *cos_x, const double *cos_y, const double *cos_z, void *G, void *Gn,
                           hipStream_t stream);
 
-// Copy the spectrum out as a dense (nz+1)(ny+1)(nx+1) octant.
-hipError_t green_export(int nx, int ny, int nz, int prec, const void *G, const void *Gn, void *dst,
+// Copy the spectrum out as a dense (nz+1)(ny+1)(nx+1) octant, kx fastest,
+// whichever layout it is kept in.
+hipError_t green_export(int nx, int ny, int nz, int prec, int gz, const void *G, const void *Gn, void *dst,
                         hipStream_t stream);
 
 }  // namespace pspfft

@@ -40,7 +40,12 @@ struct LineFFT {
     static __device__ __forceinline__ void gather(cx<T> *v, const cx<T> *lds, int ldsw_, int c, int t, int NB_) {
         const int NB = CNB ? CNB : NB_;
         const int ldsw = CLDSW ? CLDSW : ldsw_;
-        if constexpr (ROW) {
+        if constexpr (ROW && CNB != 0 && CNB % 16 == 0) {
+            // P = t + NB*m with NB a multiple of 16: P + P/16 = t + t/16 + m*(NB + NB/16)
+            const cx<T> *p0 = lds + c * ldsw + t + (t >> 4);
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = p0[m * (CNB + CNB / 16)];
+        } else if constexpr (ROW) {
             const cx<T> *row = lds + c * ldsw;
 #pragma unroll
             for (int m = 0; m < E; ++m) {
@@ -93,7 +98,16 @@ struct LineFFT {
             dft<R, DIR>(x);
             if constexpr (TO_LDS) {
                 const int base = q * Ns * R + k;  // output r goes to position base + r*Ns
-                if constexpr (ROW) {
+                if constexpr (ROW && ((CNS != 0 && CNS % 16 == 0) || (!TW && 16 % R == 0))) {
+                    // Ns a multiple of 16: P + P/16 = base + base/16 + r*(Ns + Ns/16); first
+                    // stage (Ns = 1, base = b*R) with R dividing 16: base + base/16 + r
+                    constexpr int RS = TW ? CNS + CNS / 16 : 1;
+                    cx<T> *p0 = lds + c * ldsw + base + (base >> 4);
+                    sfor<0, R>([&](auto rc) {
+                        constexpr int r = decltype(rc)::value;
+                        p0[r * RS] = x[r];
+                    });
+                } else if constexpr (ROW) {
                     cx<T> *row = lds + c * ldsw;
                     sfor<0, R>([&](auto rc) {
                         constexpr int r = decltype(rc)::value;
@@ -122,7 +136,16 @@ struct LineFFT {
     // twl: stage twiddle tables in LDS, published by the first barrier.
     // LEAD: open with a barrier so that earlier readers of the line's LDS
     // region are done; a caller that has just passed a barrier can skip it.
-    template <int K, bool LEAD = true>
+    // WAVE: every line lies within one wavefront (its LDS region too), so the
+    // exchanges need only the wavefront's own in-order LDS accesses; the
+    // barriers become compiler ordering points.
+    template <bool WAVE>
+    static __device__ __forceinline__ void sync() {
+        if constexpr (WAVE) __builtin_amdgcn_wave_barrier();
+        else __syncthreads();
+    }
+
+    template <int K, bool LEAD = true, bool WAVE = false>
     static __device__ __forceinline__ void run(cx<T> *v, const AxisPlan &ax, cx<T> *lds, int ldsw,
                                                const cx<T> *twl, int c, int t) {
         const int NB = CNB ? CNB : ax.NB;
@@ -131,35 +154,35 @@ struct LineFFT {
         } else if constexpr (CNB == K) {
             // two stages, radix E then K: the second has Ns = E and its twiddles
             // follow the E - 1 entries of the first
-            if constexpr (LEAD) __syncthreads();  // earlier readers of LDS are done
+            if constexpr (LEAD) sync<WAVE>();  // earlier readers of LDS are done
             stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
-            __syncthreads();
+            sync<WAVE>();
             gather(v, lds, ldsw, c, t, NB);
             stage<K, true, false, E>(v, E, 0u, twl + (E - 1), lds, ldsw, c, t, NB);
         } else if constexpr (CNB != 0) {
             // three stages, radices E, M, K (CNB = M*K): Ns = 1, E, E*M; the
             // twiddle tables follow one another (E - 1 and E*(M - 1) entries)
             static_assert(CNB == M * K, "compile-time lines have two or three stages");
-            if constexpr (LEAD) __syncthreads();
+            if constexpr (LEAD) sync<WAVE>();
             stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
-            __syncthreads();
+            sync<WAVE>();
             gather(v, lds, ldsw, c, t, NB);
-            __syncthreads();
+            sync<WAVE>();
             stage<M, true, true, E>(v, E, 0u, twl + (E - 1), lds, ldsw, c, t, NB);
-            __syncthreads();
+            sync<WAVE>();
             gather(v, lds, ldsw, c, t, NB);
             stage<K, true, false, E * M>(v, E * M, 0u, twl + (E - 1) + E * (M - 1), lds, ldsw, c, t, NB);
         } else {
-            if constexpr (LEAD) __syncthreads();  // earlier readers of LDS are done
+            if constexpr (LEAD) sync<WAVE>();  // earlier readers of LDS are done
             stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
             const int last = ax.nst - 1;
             for (int s = 1; s < last; ++s) {
-                __syncthreads();
+                sync<WAVE>();
                 gather(v, lds, ldsw, c, t, NB);
-                __syncthreads();
+                sync<WAVE>();
                 stage<M, true, true>(v, ax.Ns[s], ax.magic[s], twl + ax.twoff[s], lds, ldsw, c, t, NB);
             }
-            __syncthreads();
+            sync<WAVE>();
             gather(v, lds, ldsw, c, t, NB);
             stage<K, true, false>(v, ax.Ns[last], ax.magic[last], twl + ax.twoff[last], lds, ldsw, c, t, NB);
         }
@@ -249,7 +272,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr int H = E / 2;  // registers m < H hold the first half of the line
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
     constexpr int CNB = FIX == 2 ? K : (FIX == 3 ? (E & -E) * K : 0);
-    constexpr int FTILE = fix_tile(sizeof(T) == 4 ? 0 : 1, ROW, CNB);
+    constexpr int FTILE = fix_tile(sizeof(T) == 4 ? 0 : 1, MODE, CNB);
     constexpr int CL = E * CNB;  // line length when compile-time
     constexpr int CLDSW = FIX ? (ROW ? row_stride(CL, CNB, CSZ) : FTILE + 1) : 0;
     using FFT_F = LineFFT<T, E, -1, ROW, CNB, CLDSW>;
@@ -541,7 +564,9 @@ struct ZLine {
     int active;
 };
 
-template <typename T, int E, int NB, int TILE>
+// GZ: the spectrum is stored kz-fastest (octant index (kyo*nx + kx)*(nz+1) + kz,
+// Nyquist column kyo*(nz+1) + kz), for lanes that walk along a line.
+template <typename T, int E, int NB, int TILE, bool GZ = false>
 __device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int c, int t) {
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
     int sgi = 0;
@@ -591,8 +616,14 @@ __device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int 
     // G~ is even in ky and kz: octant index min(k, 2n - k)
     const int kyo = ky <= ny ? ky : 2 * ny - ky;
     zl.g = as_global(static_cast<const char *>(nyq ? pl.Gn : pl.G));
-    const size_t gb = nyq ? static_cast<size_t>(kyo) : static_cast<size_t>(kyo) * nx + kx;
-    const size_t gs = nyq ? static_cast<size_t>(ny + 1) : static_cast<size_t>(ny + 1) * nx;
+    size_t gb, gs;
+    if constexpr (GZ) {
+        gb = (nyq ? static_cast<size_t>(kyo) : static_cast<size_t>(kyo) * nx + kx) * (pl.nz + 1);
+        gs = 1;
+    } else {
+        gb = nyq ? static_cast<size_t>(kyo) : static_cast<size_t>(kyo) * nx + kx;
+        gs = nyq ? static_cast<size_t>(ny + 1) : static_cast<size_t>(ny + 1) * nx;
+    }
     zl.glo = zl.active ? static_cast<uint32_t>((gb + t * gs) * sizeof(T)) : 0u;
     zl.ghi = zl.active ? static_cast<uint32_t>((gb + (NB - t) * gs) * sizeof(T)) : 0u;
     zl.gstep = static_cast<uint32_t>(static_cast<size_t>(NB) * gs * sizeof(T));
@@ -613,7 +644,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
     constexpr int H = E / 2;
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
     constexpr int NB = FIX == 2 ? K : (E & -E) * K;
-    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, false, NB);
+    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, Z_CONV, NB);
     constexpr int LDSW = TILE + 1;
     using FFT_F = LineFFT<T, E, -1, false, NB, LDSW>;
     using FFT_I = LineFFT<T, E, +1, false, NB, LDSW>;
@@ -679,6 +710,136 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
         cur = fol;
         bid = nbid;
     }
+}
+
+// Z_CONV for lines of 64 threads (radices E, M, K with M*K = 64): wavefront w
+// holds line w of the tile, so the stage exchanges stay inside the wavefront
+// and need no workgroup barrier.  The tile's stored half is loaded with
+// adjacent lanes on adjacent lines (128-byte row segments) and transposed
+// through each line's LDS row; the results go back the same way.  The
+// spectrum is stored kz-fastest for such plans, so each wavefront reads its
+// line's values in contiguous runs.  Persistent with the next tile's loads
+// issued before the current tile's stores, as in zconv_kernel.
+template <typename T, int E, int K>
+__global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zconv_wave_kernel(const LaunchArgs args) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
+    constexpr int H = E / 2;
+    constexpr int NB = (E & -E) * K;
+    static_assert(NB == 64, "one line per wavefront");
+    constexpr int L = E * NB;
+    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, Z_CONV, NB);
+    constexpr int S = wave_line_stride(L);
+    using FFT_F = LineFFT<T, E, -1, true, NB, S>;
+    using FFT_I = LineFFT<T, E, +1, true, NB, S>;
+
+    int bid = static_cast<int>(blockIdx.x);
+    if (bid >= args.nwg) return;
+    const int tid = threadIdx.x;
+    const int cc = tid & (TILE - 1), tc = tid >> __builtin_ctz(TILE);  // adjacent lanes on adjacent lines
+    const int cw = tid >> 6, tw = tid & 63;                          // wavefront cw holds line cw
+    const AxisPlan &ax0 = args.p[0].plan->ax[2];
+    cx<T> *twl = lds + TILE * S;
+    copy_to_lds<T>(twl, ax0.tw, ax0.ntw);  // published by the first barrier below
+    // position P = t + 64m of a line's row sits at P + P/16 = t + t/16 + 68m
+    constexpr int RM = NB + NB / 16;
+    cx<T> *rowc = lds + cc * S + tc + (tc >> 4);
+    cx<T> *roww = lds + cw * S + tw + (tw >> 4);
+
+    auto load_g = [](const ZLine<T> &zl, T *gv) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const uint32_t idx = m < H ? m : E - m - 1;
+            gv[m] = *reinterpret_cast<const gbl<T> *>(zl.g + ((m < H ? zl.glo : zl.ghi) + idx * zl.gstep));
+        }
+    };
+    ZLine<T> cur = z_line<T, E, NB, TILE>(args, bid, cc, tc);
+    T gnx[E];
+    {
+        cx<T> first[H];
+#pragma unroll
+        for (int m = 0; m < H; ++m) first[m] = cur.lane[m];
+        load_g(z_line<T, E, NB, TILE, true>(args, bid, cw, tw), gnx);
+#pragma unroll
+        for (int m = 0; m < H; ++m) rowc[m * RM] = first[m];
+    }
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // nothing outstanding on entry (vmcnt 0)
+    for (;;) {
+        __syncthreads();  // the tile is in the rows (and, first time, the twiddles)
+        cx<T> v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = m < H ? roww[m * RM] : cx<T>{T(0), T(0)};
+        FFT_F::template run<K, true, true>(v, ax0, lds, S, twl, cw, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = scale(v[m], gnx[m]);
+        // the next tile's line and spectrum values, before this tile's stores
+        const int nbid = bid + static_cast<int>(gridDim.x);
+        const bool more = nbid < args.nwg;
+        const int fbid = more ? nbid : bid;
+        const ZLine<T> fol = z_line<T, E, NB, TILE>(args, fbid, cc, tc);
+        // FP64: the line is loaded after this tile's stores (eight more 16-byte
+        // values held across the inverse transform do not stay in registers)
+        constexpr bool PF = sizeof(T) == 4;
+        cx<T> nxt[PF ? H : 1];
+        if constexpr (PF) {
+#pragma unroll
+            for (int m = 0; m < H; ++m) nxt[m] = fol.lane[m];
+        }
+        load_g(z_line<T, E, NB, TILE, true>(args, fbid, cw, tw), gnx);
+        FFT_I::template run<K, true, true>(v, ax0, lds, S, twl, cw, tw);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int m = 0; m < H; ++m) roww[m * RM] = v[m];
+        __syncthreads();  // results are in the rows
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const uint32_t off = static_cast<uint32_t>(cur.lane.lane) +
+                                 static_cast<uint32_t>(m) * static_cast<uint32_t>(cur.lane.step);
+            buffer_store<T>(rowc[m * RM], cur.lane.base, cur.bytes, cur.active ? off : 0xfffffff0u);
+        }
+        if (!more) break;
+        __syncthreads();  // the rows have been read
+        if constexpr (PF) {
+#pragma unroll
+            for (int m = 0; m < H; ++m) rowc[m * RM] = nxt[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < H; ++m) rowc[m * RM] = fol.lane[m];
+        }
+        cur = fol;
+        bid = nbid;
+    }
+}
+
+template <typename T, int E, int K>
+hipError_t launch_zconv_wave(const LaunchArgs &args, hipStream_t stream) {
+    constexpr int kMaxDevices = 64;
+    constexpr int NB = (E & -E) * K, L = E * NB;
+    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, Z_CONV, NB);
+    constexpr int block = TILE * NB;
+    constexpr size_t lds = static_cast<size_t>(TILE * wave_line_stride(L) + L - 1) * sizeof(cx<T>);
+    static_assert(lds <= 160 * 1024, "tile rows and twiddles fit the LDS");
+    static int resident[kMaxDevices] = {0};
+    auto fn = zconv_wave_kernel<T, E, K>;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (resident[dev] == 0) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024);
+        if (e != hipSuccess) return e;
+        int p = 0, c = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, fn, block, lds);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        resident[dev] = (p > 0 ? p : 1) * (c > 0 ? c : 1);
+    }
+    int grid = resident[dev];
+    if (grid > args.nwg) grid = args.nwg;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, stream, args);
+    return hipGetLastError();
 }
 
 // Where the persistent z convolution runs (PSPFFT_ZCONV_PERSIST: 0 never, 1
@@ -751,7 +912,9 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
         case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
         case Y_FWD: return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
         case Z_CONV:
-            if constexpr (FIX != 0) {
+            if constexpr (FIX == 3 && (E & -E) * K == 64) {
+                return launch_zconv_wave<T, E, K>(args, stream);
+            } else if constexpr (FIX != 0) {
                 hipError_t e = hipSuccess;
                 if (launch_zconv<T, E, K, FIX>(args, block, lds, stream, &e)) return e;
             }
@@ -772,7 +935,7 @@ hipError_t launch_fix(int mode, int fix, const LaunchArgs &args, int grid, int b
     constexpr int M = E & -E;
     if constexpr (K > 1) {
         if (fix == 2) return launch_mode<T, E, K, 2>(mode, args, grid, block, lds, stream);
-        if constexpr (fix_tile(prec, false, M * K) * M * K <= max_block_for(prec, E)) {
+        if constexpr (fix_tile(prec, Y_FWD, M * K) * M * K <= max_block_for(prec, E)) {
             if (fix == 3) return launch_mode<T, E, K, 3>(mode, args, grid, block, lds, stream);
         }
     }

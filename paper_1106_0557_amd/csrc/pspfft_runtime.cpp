@@ -279,6 +279,18 @@ bool arrays_below_4gb(pspfft_plan_t p) {
     return ws_bytes(p->n, p->prec) < lim && nx * ny * nz * r < lim && (nz + 1) * (ny + 1) * nx * r < lim;
 }
 
+// The z pass runs by wavefront-owned lines (zconv_wave_kernel) where its lines
+// have three stages E, M, K with M*K = 64 threads, the compile-time instance
+// exists and every array is below 4 GB.  Such plans keep the spectrum
+// kz-fastest, and their z launches always take that kernel.
+bool z_wave_lines(pspfft_plan_t p) {
+    const AxisPlan &az = p->host.ax[2];
+    const int prec = p->host.prec, M = az.E & -az.E;
+    return az.nst == 3 && az.R[1] == M && az.NB == 64 && M * az.R[2] == 64 &&
+           pspfft::fix_tile(prec, pspfft::Z_CONV, 64) * 64 <= pspfft::max_block_for(prec, az.E) &&
+           pspfft::fix_tile(prec, pspfft::Y_FWD, 64) * 64 <= pspfft::max_block_for(prec, az.E) && arrays_below_4gb(p);
+}
+
 // Lines (main, Nyquist) that a pass processes for one problem.
 void pass_lines(int mode, const int n[3], long &main, long &nyq) {
     const long nx = n[0], ny = n[1], nz = n[2];
@@ -297,15 +309,17 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
                            hipStream_t stream) {
     const int axis = pspfft::pass_axis(mode);
     const bool row = axis == 0;
-    // One kernel per (precision, radix family E, last-stage radix K) of the pass axis.
-    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    // One kernel per (precision, radix family E, last-stage radix K, spectrum layout).
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
     for (int i : all) {
         const AxisPlan &ax = plans[i]->host.ax[axis];
         const int K = ax.nst == 1 ? 1 : ax.R[ax.nst - 1];
-        groups[{static_cast<int>(plans[i]->prec), ax.E, K}].push_back(i);
+        const int gz = mode == pspfft::Z_CONV ? plans[i]->host.gz : 0;
+        groups[{static_cast<int>(plans[i]->prec), ax.E, K, gz}].push_back(i);
     }
     for (auto &kv : groups) {
         const int prec = std::get<0>(kv.first), E = std::get<1>(kv.first), K = std::get<2>(kv.first);
+        const bool gz = std::get<3>(kv.first) != 0;
         std::vector<int> idx = kv.second;
         // problems of one plan next to each other: they form a segment sharing spectrum reads
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
@@ -319,15 +333,19 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
             const size_t c1 = std::min(idx.size(), c0 + pspfft::kMaxProblems);
             int block = 0, nbmax = 1;
             for (size_t j = c0; j < c1; ++j) nbmax = std::max(nbmax, plans[idx[j]]->host.ax[axis].NB);
-            const int tile_target = line_tile(mode, pspfft::fix_tile(prec, row, nbmax));
+            // (a kz-fastest spectrum needs the compile-time tile: no override)
+            const int tile_target = gz ? pspfft::fix_tile(prec, mode, nbmax)
+                                       : line_tile(mode, pspfft::fix_tile(prec, mode, nbmax));
             for (size_t j = c0; j < c1; ++j) block = std::max(block, tile_target * plans[idx[j]]->host.ax[axis].NB);
             block = std::min(std::max(block, 64), bmax);
             auto lds_need = [&](int blk) {
                 size_t need = 0;
                 for (size_t j = c0; j < c1; ++j) {
                     const AxisPlan &ax = plans[idx[j]]->host.ax[axis];
-                    const size_t e = static_cast<size_t>(pspfft::data_elems(row, ax.L, ax.NB, blk, csz)) + ax.ntw +
-                                     (row ? ax.L : 0);
+                    // wavefront-owned z lines: one row of wave_line_stride(L) per line
+                    const size_t data = gz ? static_cast<size_t>(blk / ax.NB) * pspfft::wave_line_stride(ax.L)
+                                           : static_cast<size_t>(pspfft::data_elems(row, ax.L, ax.NB, blk, csz));
+                    const size_t e = data + ax.ntw + (row ? ax.L : 0);
                     need = std::max(need, e * csz);
                 }
                 return need;
@@ -383,13 +401,14 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
                 if (a0.nst == 2) fix = 2;
                 else if (a0.nst == 3 && a0.R[1] == M) fix = 3;
                 const int cnb = fix == 2 ? K : M * K;
-                if (fix && block != pspfft::fix_tile(prec, row, cnb) * cnb) fix = 0;
-                if (fix == 3 && pspfft::fix_tile(prec, false, cnb) * cnb > pspfft::max_block_for(prec, E)) fix = 0;
+                if (fix && block != pspfft::fix_tile(prec, mode, cnb) * cnb) fix = 0;
+                if (fix == 3 && pspfft::fix_tile(prec, mode, cnb) * cnb > pspfft::max_block_for(prec, E)) fix = 0;
                 for (size_t j = c0; j < c1 && fix; ++j) {
                     const AxisPlan &ax = plans[idx[j]]->host.ax[axis];
                     if (ax.nst != a0.nst || ax.NB != cnb || !arrays_below_4gb(plans[idx[j]])) fix = 0;
                 }
             }
+            if (gz && fix != 3) return PSPFFT_ERR_UNSUPPORTED_SIZE;  // only zconv_wave_kernel reads that layout
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "
                           "threads, %zu B LDS", mode, prec, E, K, fix, args.count, args.nseg, wg, block, lds);
             if (pspfft::launch_pass(mode, prec, E, K, fix, args, grid, block, lds, stream) != hipSuccess)
@@ -573,6 +592,7 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
         while (zb < cap && nbz % (2 * zb) == 0) zb *= 2;
         p->host.zb = zb;
     }
+    p->host.gz = z_wave_lines(p) ? 1 : 0;
     // fused x-y plane kernels: nx == ny = E*K (at most two stages) and the plane fits in LDS
     {
         const AxisPlan &ax = p->host.ax[0];
@@ -612,7 +632,8 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
             hipMemcpy(cz, tz.data(), tz.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
             return PSPFFT_ERR_DEVICE;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PSPFFT_ERR_DEVICE;
-        if (pspfft::green_spectrum(nx, ny, nz, p->h, p->host.prec, static_cast<double *>(a), static_cast<double *>(b),
+        if (pspfft::green_spectrum(nx, ny, nz, p->h, p->host.prec, p->host.gz, static_cast<double *>(a),
+                                   static_cast<double *>(b),
                                    static_cast<const double *>(cx), static_cast<const double *>(cy),
                                    static_cast<const double *>(cz), p->G, p->Gn, s) != hipSuccess)
             return PSPFFT_ERR_DEVICE;
@@ -755,6 +776,8 @@ size_t pspfft_pass_bytes(pspfft_plan_t plan, pspfft_pass pass) {
 
 int pspfft_plan_fused(pspfft_plan_t plan) { return plan && plan->fused ? 1 : 0; }
 
+int pspfft_plan_spectrum_kz_fastest(pspfft_plan_t plan) { return plan && plan->host.gz ? 1 : 0; }
+
 int pspfft_workspace_ztile(pspfft_plan_t plan) { return plan ? plan->host.zb : 0; }
 
 pspfft_status pspfft_plan_info(pspfft_plan_t plan, int dims[3], double h[3], pspfft_precision *prec) {
@@ -769,8 +792,8 @@ pspfft_status pspfft_plan_info(pspfft_plan_t plan, int dims[3], double h[3], psp
 
 pspfft_status pspfft_plan_green(pspfft_plan_t plan, void *dst, hipStream_t stream) {
     if (!plan || !dst) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (pspfft::green_export(plan->n[0], plan->n[1], plan->n[2], plan->host.prec, plan->G, plan->Gn, dst, stream) !=
-        hipSuccess)
+    if (pspfft::green_export(plan->n[0], plan->n[1], plan->n[2], plan->host.prec, plan->host.gz, plan->G, plan->Gn,
+                             dst, stream) != hipSuccess)
         return PSPFFT_ERR_DEVICE;
     return PSPFFT_OK;
 }

@@ -126,6 +126,7 @@ def test_null_handles(lib):
     assert lib.pspfft_plan_info(None, None, None, None) == 1
     assert lib.pspfft_plan_green(None, None, None) == 1
     assert lib.pspfft_plan_fused(None) == 0
+    assert lib.pspfft_plan_spectrum_kz_fastest(None) == 0
     assert lib.pspfft_workspace_ztile(None) == 0
     # an empty batch is a no-op; a negative count is an error
     assert lib.pspfft_solve_batched(0, None, None, None, None, None) == 0

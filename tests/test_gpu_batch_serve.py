@@ -71,8 +71,10 @@ def test_mixed_precision_batch_matches_single():
     import paper_1106_0557_amd as ps
 
     say("[mixed precision batch]")
+    # (16, 8, 512): spectrum kz-fastest, z lines by wavefront
     cases = [((32, 24, 16), torch.float32), ((32, 24, 16), torch.float64), ((48, 48, 48), torch.float64),
-             ((16, 36, 20), torch.float32)]
+             ((16, 36, 20), torch.float32), ((16, 8, 512), torch.float32), ((16, 8, 512), torch.float64),
+             ((16, 8, 256), torch.float32)]
     ws, S, P, plans = [], [], [], []
     for k, (n, dt) in enumerate(cases):
         pl = ps.Plan(*n, h=(0.1, 0.2, 0.3), dtype=dt)

@@ -50,8 +50,10 @@ def gpu_solve(n, h, S, dtype):
 
 # ---------------------------------------------------------------- spectrum --
 
+# (16, 8, 512): z lines of 1024 = 16*16*4, kept kz-fastest
 @pytest.mark.parametrize("n,h", [((16, 16, 16), (1 / 16,) * 3), ((24, 10, 16), (0.3, 0.2, 0.5)),
-                                 ((24, 18, 20), (0.05, 0.07, 0.06)), ((36, 8, 40), (1.0, 1.0, 2.0))])
+                                 ((24, 18, 20), (0.05, 0.07, 0.06)), ((36, 8, 40), (1.0, 1.0, 2.0)),
+                                 ((16, 8, 512), (0.02, 0.03, 0.025))])
 def test_green_spectrum_matches_oracle(n, h):
     from paper_1106_0557_amd import Plan
 
@@ -59,6 +61,7 @@ def test_green_spectrum_matches_oracle(n, h):
     want, imag_max, abs_max = oracle.green_hat_octant(n, h)
     for dtype, tol in ((torch.float64, FP64_TOL), (torch.float32, 1e-7)):
         plan = Plan(*n, h=h, dtype=dtype)
+        assert plan.spectrum_kz_fastest == (n[2] == 512)
         got = plan.green().double().cpu().numpy()
         plan.close()
         err = np.abs(got - want).max() / abs_max
@@ -193,6 +196,12 @@ THREE_STAGE = [(16, 8, 256), (16, 8, 512), (16, 8, 288), (16, 192, 8), (16, 144,
 @pytest.mark.parametrize("n", THREE_STAGE)
 def test_three_stage_lines_match_oracle(n):
     say(f"[three-stage] n={n}")
+    from paper_1106_0557_amd import Plan
+
+    for dt in (torch.float32, torch.float64):  # z lines of 1024: one wavefront per line
+        p = Plan(*n, h=0.1, dtype=dt)
+        assert p.spectrum_kz_fastest == (n[2] == 512)
+        p.close()
     h = (0.02, 0.03, 0.025)
     S = sources.random_field(n, seed=sum(n) + 1).numpy()
     ref = oracle.solve_fft(S, h)
