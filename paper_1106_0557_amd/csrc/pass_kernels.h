@@ -712,21 +712,23 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
     }
 }
 
-// Z_CONV for lines of 64 threads (radices E, M, K with M*K = 64): wavefront w
-// holds line w of the tile, so the stage exchanges stay inside the wavefront
-// and need no workgroup barrier.  The tile's stored half is loaded with
-// adjacent lanes on adjacent lines (128-byte row segments) and transposed
-// through each line's LDS row; the results go back the same way.  The
-// spectrum is stored kz-fastest for such plans, so each wavefront reads its
-// line's values in contiguous runs.  Persistent with the next tile's loads
-// issued before the current tile's stores, as in zconv_kernel.
-template <typename T, int E, int K>
+// Z_CONV for lines of 32 or 64 threads (radices E, M, K with M*K = NB): each
+// line lies within one wavefront (wavefront w holds lines w*64/NB onwards), so
+// the stage exchanges stay inside the wavefront and need no workgroup barrier.
+// The tile's stored half is loaded with adjacent lanes on adjacent lines
+// (128-byte row segments) and transposed through each line's LDS row; the
+// results go back the same way.  The spectrum is stored kz-fastest for such
+// plans, so each line's values are read in contiguous runs.  PERSIST: the
+// workgroup walks tiles b, b + gridDim.x, ... and issues the next tile's loads
+// before the current tile's stores, as in zconv_kernel; otherwise it takes one
+// tile.
+template <typename T, int E, int K, bool PERSIST>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zconv_wave_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
     constexpr int H = E / 2;
     constexpr int NB = (E & -E) * K;
-    static_assert(NB == 64, "one line per wavefront");
+    static_assert(NB == 32 || NB == 64, "lines of 32 or 64 threads");
     constexpr int L = E * NB;
     constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, Z_CONV, NB);
     constexpr int S = wave_line_stride(L);
@@ -737,11 +739,11 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
     if (bid >= args.nwg) return;
     const int tid = threadIdx.x;
     const int cc = tid & (TILE - 1), tc = tid >> __builtin_ctz(TILE);  // adjacent lanes on adjacent lines
-    const int cw = tid >> 6, tw = tid & 63;                          // wavefront cw holds line cw
+    const int cw = tid >> __builtin_ctz(NB), tw = tid & (NB - 1);       // line cw lies in one wavefront
     const AxisPlan &ax0 = args.p[0].plan->ax[2];
     cx<T> *twl = lds + TILE * S;
     copy_to_lds<T>(twl, ax0.tw, ax0.ntw);  // published by the first barrier below
-    // position P = t + 64m of a line's row sits at P + P/16 = t + t/16 + 68m
+    // position P = t + NB*m of a line's row sits at P + P/16 = t + t/16 + m*(NB + NB/16)
     constexpr int RM = NB + NB / 16;
     cx<T> *rowc = lds + cc * S + tc + (tc >> 4);
     cx<T> *roww = lds + cw * S + tw + (tw >> 4);
@@ -763,7 +765,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
 #pragma unroll
         for (int m = 0; m < H; ++m) rowc[m * RM] = first[m];
     }
-    __builtin_amdgcn_s_waitcnt(0x0f70);  // nothing outstanding on entry (vmcnt 0)
+    if constexpr (PERSIST) __builtin_amdgcn_s_waitcnt(0x0f70);  // nothing outstanding on entry (vmcnt 0)
     for (;;) {
         __syncthreads();  // the tile is in the rows (and, first time, the twiddles)
         cx<T> v[E];
@@ -774,18 +776,21 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
         for (int m = 0; m < E; ++m) v[m] = scale(v[m], gnx[m]);
         // the next tile's line and spectrum values, before this tile's stores
         const int nbid = bid + static_cast<int>(gridDim.x);
-        const bool more = nbid < args.nwg;
+        const bool more = PERSIST && nbid < args.nwg;
         const int fbid = more ? nbid : bid;
-        const ZLine<T> fol = z_line<T, E, NB, TILE>(args, fbid, cc, tc);
         // FP64: the line is loaded after this tile's stores (eight more 16-byte
         // values held across the inverse transform do not stay in registers)
-        constexpr bool PF = sizeof(T) == 4;
+        constexpr bool PF = PERSIST && sizeof(T) == 4;
+        ZLine<T> fol = cur;
         cx<T> nxt[PF ? H : 1];
-        if constexpr (PF) {
+        if constexpr (PERSIST) {
+            fol = z_line<T, E, NB, TILE>(args, fbid, cc, tc);
+            if constexpr (PF) {
 #pragma unroll
-            for (int m = 0; m < H; ++m) nxt[m] = fol.lane[m];
+                for (int m = 0; m < H; ++m) nxt[m] = fol.lane[m];
+            }
+            load_g(z_line<T, E, NB, TILE, true>(args, fbid, cw, tw), gnx);
         }
-        load_g(z_line<T, E, NB, TILE, true>(args, fbid, cw, tw), gnx);
         FFT_I::template run<K, true, true>(v, ax0, lds, S, twl, cw, tw);
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -811,6 +816,10 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
     }
 }
 
+inline int zconv_persist_mode();
+
+// The wavefront-owned z convolution: persistent where one workgroup fills a
+// compute unit (zconv_persist_mode), otherwise one tile per workgroup.
 template <typename T, int E, int K>
 hipError_t launch_zconv_wave(const LaunchArgs &args, hipStream_t stream) {
     constexpr int kMaxDevices = 64;
@@ -819,26 +828,35 @@ hipError_t launch_zconv_wave(const LaunchArgs &args, hipStream_t stream) {
     constexpr int block = TILE * NB;
     constexpr size_t lds = static_cast<size_t>(TILE * wave_line_stride(L) + L - 1) * sizeof(cx<T>);
     static_assert(lds <= 160 * 1024, "tile rows and twiddles fit the LDS");
-    static int resident[kMaxDevices] = {0};
-    auto fn = zconv_wave_kernel<T, E, K>;
+    static int per_cu[kMaxDevices] = {0}, cus[kMaxDevices] = {0};
+    auto fp = zconv_wave_kernel<T, E, K, true>;
+    auto fo = zconv_wave_kernel<T, E, K, false>;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    if (resident[dev] == 0) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                160 * 1024);
-        if (e != hipSuccess) return e;
+    if (per_cu[dev] == 0) {
+        for (auto f : {fp, fo}) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024);
+            if (e != hipSuccess) return e;
+        }
         int p = 0, c = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, fn, block, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, fp, block, lds);
         if (e != hipSuccess) return e;
         e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
-        resident[dev] = (p > 0 ? p : 1) * (c > 0 ? c : 1);
+        per_cu[dev] = p > 0 ? p : 1;
+        cus[dev] = c > 0 ? c : 1;
     }
-    int grid = resident[dev];
-    if (grid > args.nwg) grid = args.nwg;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, stream, args);
+    const int mode = zconv_persist_mode();
+    if (mode == 1 || (mode < 0 && per_cu[dev] == 1)) {
+        int grid = per_cu[dev] * cus[dev];
+        if (grid > args.nwg) grid = args.nwg;
+        hipLaunchKernelGGL(fp, dim3(grid), dim3(block), lds, stream, args);
+    } else {
+        hipLaunchKernelGGL(fo, dim3(args.nwg), dim3(block), lds, stream, args);
+    }
     return hipGetLastError();
 }
 
@@ -912,7 +930,7 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
         case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
         case Y_FWD: return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
         case Z_CONV:
-            if constexpr (FIX == 3 && (E & -E) * K == 64) {
+            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64)) {
                 return launch_zconv_wave<T, E, K>(args, stream);
             } else if constexpr (FIX != 0) {
                 hipError_t e = hipSuccess;

@@ -280,15 +280,15 @@ bool arrays_below_4gb(pspfft_plan_t p) {
 }
 
 // The z pass runs by wavefront-owned lines (zconv_wave_kernel) where its lines
-// have three stages E, M, K with M*K = 64 threads, the compile-time instance
-// exists and every array is below 4 GB.  Such plans keep the spectrum
+// have three stages E, M, K with M*K = 32 or 64 threads, the compile-time
+// instance exists and every array is below 4 GB.  Such plans keep the spectrum
 // kz-fastest, and their z launches always take that kernel.
 bool z_wave_lines(pspfft_plan_t p) {
     const AxisPlan &az = p->host.ax[2];
-    const int prec = p->host.prec, M = az.E & -az.E;
-    return az.nst == 3 && az.R[1] == M && az.NB == 64 && M * az.R[2] == 64 &&
-           pspfft::fix_tile(prec, pspfft::Z_CONV, 64) * 64 <= pspfft::max_block_for(prec, az.E) &&
-           pspfft::fix_tile(prec, pspfft::Y_FWD, 64) * 64 <= pspfft::max_block_for(prec, az.E) && arrays_below_4gb(p);
+    const int prec = p->host.prec, M = az.E & -az.E, NB = az.NB;
+    return az.nst == 3 && az.R[1] == M && (NB == 32 || NB == 64) && M * az.R[2] == NB &&
+           pspfft::fix_tile(prec, pspfft::Z_CONV, NB) * NB <= pspfft::max_block_for(prec, az.E) &&
+           pspfft::fix_tile(prec, pspfft::Y_FWD, NB) * NB <= pspfft::max_block_for(prec, az.E) && arrays_below_4gb(p);
 }
 
 // Lines (main, Nyquist) that a pass processes for one problem.
