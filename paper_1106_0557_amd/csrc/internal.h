@@ -86,6 +86,7 @@ struct LaunchArgs {
     int nseg;         // segments
     int nwg;          // workgroups doing work (the grid may be padded to a multiple of 8)
     int xcd_remap;    // renumber workgroups so each XCD gets a contiguous range
+    int wave_z;       // z pass: spectra kz-fastest, lines kept within one wavefront
     Segment seg[kMaxProblems];
     ProbArg p[kMaxProblems];
 };
@@ -146,6 +147,13 @@ __host__ __device__ constexpr int fix_tile(int prec, int mode, int nb) {
 
 __host__ __device__ constexpr int max_block_for(int prec, int E) {
     return prec == 0 ? (E == 16 ? 1024 : (E <= 24 ? 512 : 256)) : (E == 16 ? 512 : 256);
+}
+
+// LDS bytes of the wavefront-owned z convolution for lines of length L = E*NB:
+// one row per line of the tile, then the stage twiddles.
+__host__ __device__ constexpr size_t wave_z_lds_bytes(int prec, int E, int NB) {
+    const int L = E * NB;
+    return static_cast<size_t>(fix_tile(prec, Z_CONV, NB) * wave_line_stride(L) + L - 1) * (prec == 0 ? 8 : 16);
 }
 
 // Fused plane kernels (x and y transforms of one z plane per workgroup) for

@@ -712,7 +712,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
     }
 }
 
-// Z_CONV for lines of 32 or 64 threads (radices E, M, K with M*K = NB): each
+// Z_CONV for lines of 16, 32 or 64 threads (radices E, M, K with M*K = NB): each
 // line lies within one wavefront (wavefront w holds lines w*64/NB onwards), so
 // the stage exchanges stay inside the wavefront and need no workgroup barrier.
 // The tile's stored half is loaded with adjacent lanes on adjacent lines
@@ -728,7 +728,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
     constexpr int H = E / 2;
     constexpr int NB = (E & -E) * K;
-    static_assert(NB == 32 || NB == 64, "lines of 32 or 64 threads");
+    static_assert(NB == 16 || NB == 32 || NB == 64, "lines of 16, 32 or 64 threads");
     constexpr int L = E * NB;
     constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, Z_CONV, NB);
     constexpr int S = wave_line_stride(L);
@@ -826,7 +826,8 @@ hipError_t launch_zconv_wave(const LaunchArgs &args, hipStream_t stream) {
     constexpr int NB = (E & -E) * K, L = E * NB;
     constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, Z_CONV, NB);
     constexpr int block = TILE * NB;
-    constexpr size_t lds = static_cast<size_t>(TILE * wave_line_stride(L) + L - 1) * sizeof(cx<T>);
+    constexpr size_t lds = wave_z_lds_bytes(sizeof(T) == 4 ? 0 : 1, E, NB);
+    static_assert(lds == static_cast<size_t>(TILE * wave_line_stride(L) + L - 1) * sizeof(cx<T>), "layout");
     static_assert(lds <= 160 * 1024, "tile rows and twiddles fit the LDS");
     static int per_cu[kMaxDevices] = {0}, cus[kMaxDevices] = {0};
     auto fp = zconv_wave_kernel<T, E, K, true>;
@@ -930,9 +931,11 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
         case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
         case Y_FWD: return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
         case Z_CONV:
-            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64)) {
-                return launch_zconv_wave<T, E, K>(args, stream);
-            } else if constexpr (FIX != 0) {
+            if constexpr (FIX == 3 && ((E & -E) * K == 16 || (E & -E) * K == 32 || (E & -E) * K == 64)) {
+                if (args.wave_z) return launch_zconv_wave<T, E, K>(args, stream);
+            }
+            if (args.wave_z) return hipErrorInvalidValue;  // a kz-fastest spectrum needs zconv_wave_kernel
+            if constexpr (FIX != 0) {
                 hipError_t e = hipSuccess;
                 if (launch_zconv<T, E, K, FIX>(args, block, lds, stream, &e)) return e;
             }

@@ -280,13 +280,16 @@ bool arrays_below_4gb(pspfft_plan_t p) {
 }
 
 // The z pass runs by wavefront-owned lines (zconv_wave_kernel) where its lines
-// have three stages E, M, K with M*K = 32 or 64 threads, the compile-time
-// instance exists and every array is below 4 GB.  Such plans keep the spectrum
-// kz-fastest, and their z launches always take that kernel.
+// have three stages E, M, K with M*K = 32 or 64 threads, or 16 threads where the
+// tile's rows take more than half the LDS (one workgroup per CU; measured, the
+// smaller 16-thread tiles gain nothing over the column kernel), the
+// compile-time instance exists and every array is below 4 GB.  Such plans keep
+// the spectrum kz-fastest, and their z launches always take that kernel.
 bool z_wave_lines(pspfft_plan_t p) {
     const AxisPlan &az = p->host.ax[2];
     const int prec = p->host.prec, M = az.E & -az.E, NB = az.NB;
-    return az.nst == 3 && az.R[1] == M && (NB == 32 || NB == 64) && M * az.R[2] == NB &&
+    const bool nb_ok = NB == 32 || NB == 64 || (NB == 16 && pspfft::wave_z_lds_bytes(prec, az.E, NB) > 80 * 1024);
+    return az.nst == 3 && az.R[1] == M && nb_ok && M * az.R[2] == NB &&
            pspfft::fix_tile(prec, pspfft::Z_CONV, NB) * NB <= pspfft::max_block_for(prec, az.E) &&
            pspfft::fix_tile(prec, pspfft::Y_FWD, NB) * NB <= pspfft::max_block_for(prec, az.E) && arrays_below_4gb(p);
 }
@@ -389,6 +392,7 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
             if (wg + 8 > 0x7fffffffL) return PSPFFT_ERR_UNSUPPORTED_SIZE;
             args.nwg = static_cast<int>(wg);
             args.xcd_remap = xcd_remap_mode(mode);
+            args.wave_z = gz ? 1 : 0;
             const long align = args.xcd_remap == 1 ? 8 : (args.xcd_remap == 2 ? 64 : 1);
             const int grid = static_cast<int>((wg + align - 1) / align * align);
             // compile-time geometry when every line has two stages (radices E, K)

@@ -50,6 +50,10 @@ def gpu_solve(n, h, S, dtype):
 
 # ---------------------------------------------------------------- spectrum --
 
+# z sizes whose three-stage z lines are kept within one wavefront (spectrum kz-fastest)
+WAVE_Z = (256, 288, 384, 512)
+
+
 # (16, 8, 512): z lines of 1024 = 16*16*4, kept kz-fastest
 @pytest.mark.parametrize("n,h", [((16, 16, 16), (1 / 16,) * 3), ((24, 10, 16), (0.3, 0.2, 0.5)),
                                  ((24, 18, 20), (0.05, 0.07, 0.06)), ((36, 8, 40), (1.0, 1.0, 2.0)),
@@ -61,7 +65,7 @@ def test_green_spectrum_matches_oracle(n, h):
     want, imag_max, abs_max = oracle.green_hat_octant(n, h)
     for dtype, tol in ((torch.float64, FP64_TOL), (torch.float32, 1e-7)):
         plan = Plan(*n, h=h, dtype=dtype)
-        assert plan.spectrum_kz_fastest == (n[2] in (256, 384, 512))
+        assert plan.spectrum_kz_fastest == (n[2] in WAVE_Z)
         got = plan.green().double().cpu().numpy()
         plan.close()
         err = np.abs(got - want).max() / abs_max
@@ -187,11 +191,11 @@ def test_solve_matches_oracle(n):
 
 
 # Lines of three stages (radices E, M, K) with compile-time geometry: z lines of
-# 512 (16*16*2), 1024 (16*16*4) and 768 (24*8*4), which keep each line within one
-# wavefront, 576 (36*4*4), 320 (20*4*4); y lines of 384 (24*8*2), 288 (36*4*2),
+# 512 (16*16*2), 1024 (16*16*4), 768 (24*8*4) and 576 (36*4*4), each kept within
+# one wavefront, 384 (24*8*2), 320 (20*4*4); y lines of 384 (24*8*2), 288 (36*4*2),
 # 160 (20*4*2); x rows of 512 and 384.
-THREE_STAGE = [(16, 8, 256), (16, 8, 512), (16, 8, 384), (16, 8, 288), (16, 192, 8), (16, 144, 8),
-               (20, 80, 160), (512, 8, 8), (384, 8, 8)]
+THREE_STAGE = [(16, 8, 256), (16, 8, 512), (16, 8, 384), (16, 8, 192), (16, 8, 288), (16, 192, 8),
+               (16, 144, 8), (20, 80, 160), (512, 8, 8), (384, 8, 8)]
 
 
 @pytest.mark.parametrize("n", THREE_STAGE)
@@ -199,9 +203,9 @@ def test_three_stage_lines_match_oracle(n):
     say(f"[three-stage] n={n}")
     from paper_1106_0557_amd import Plan
 
-    for dt in (torch.float32, torch.float64):  # z lines of 512, 768, 1024: within one wavefront
+    for dt in (torch.float32, torch.float64):
         p = Plan(*n, h=0.1, dtype=dt)
-        assert p.spectrum_kz_fastest == (n[2] in (256, 384, 512))
+        assert p.spectrum_kz_fastest == (n[2] in WAVE_Z)
         p.close()
     h = (0.02, 0.03, 0.025)
     S = sources.random_field(n, seed=sum(n) + 1).numpy()
