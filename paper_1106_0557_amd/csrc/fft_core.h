@@ -122,6 +122,52 @@ __device__ __forceinline__ cx<T> rot(cx<T> a) {
     }
 }
 
+// x + b*w and x - b*w for w = exp(DIR 2 pi i e / R) with e, R known at compile
+// time.  For a non-trivial w = c + i s the factor with the larger magnitude is
+// taken out (Linzer and Feig's FMA butterfly): b*w = c * (b + i b tan) or
+// s * (b cot + i b), so both results cost six multiply-adds instead of a full
+// complex product and two additions.
+template <int R, int DIR, int e, typename T>
+__device__ __forceinline__ void add_sub_rot(const cx<T> x, const cx<T> b, cx<T> &sum, cx<T> &dif) {
+    constexpr int em = ((e % R) + R) % R;
+    if constexpr (em == 0 || 2 * em == R || 4 * em == R || 4 * em == 3 * R) {
+        const cx<T> r = rot<R, DIR, e>(b);
+        sum = x + r;
+        dif = x - r;
+    } else {
+        constexpr CosSin w = turn(static_cast<long>(DIR) * em, R);
+        constexpr bool eighth = 8 * em % R == 0;  // |c| = |s|: the ratio is exactly +-1
+        constexpr bool cos_out = (w.c < 0 ? -w.c : w.c) >= (w.s < 0 ? -w.s : w.s);
+        if constexpr (cos_out) {
+            constexpr double tq = eighth ? (w.s * w.c > 0 ? 1.0 : -1.0) : w.s / w.c;
+            const T t = static_cast<T>(tq), c = static_cast<T>(w.c);
+            const cx<T> q = {b.x - b.y * t, b.y + b.x * t};  // b*w / c
+            sum = {x.x + q.x * c, x.y + q.y * c};
+            dif = {x.x - q.x * c, x.y - q.y * c};
+        } else {
+            constexpr double kq = w.c / w.s;
+            const T k = static_cast<T>(kq), sn = static_cast<T>(w.s);
+            const cx<T> q = {b.x * k - b.y, b.y * k + b.x};  // b*w / s
+            sum = {x.x + q.x * sn, x.y + q.y * sn};
+            dif = {x.x - q.x * sn, x.y - q.y * sn};
+        }
+    }
+}
+
+// Length-4 DFT of a[q] = b[q] * exp(DIR 2 pi i q k1 / R), the second layer of a
+// radix-4 Cooley-Tukey split of R, with the twiddles folded into the butterflies.
+template <int R, int DIR, int k1, typename T>
+__device__ __forceinline__ void dft4_rot(cx<T> *b) {
+    cx<T> t0, t1, t2, d;
+    add_sub_rot<R, DIR, 2 * k1>(b[0], b[2], t0, t1);
+    add_sub_rot<R, DIR, 3 * k1>(rot<R, DIR, k1>(b[1]), b[3], t2, d);
+    const cx<T> t3 = rot<4, DIR, 1>(d);
+    b[0] = t0 + t2;
+    b[2] = t0 - t2;
+    b[1] = t1 + t3;
+    b[3] = t1 - t3;
+}
+
 constexpr int first_factor(int R) {
     if (R % 4 == 0 && R > 4) return 4;
     for (int p = 2; p <= R; ++p)
@@ -187,12 +233,23 @@ __device__ __forceinline__ void dft(cx<T> *x) {
             dft<P, DIR>(u);
             sfor<0, P>([&](auto kc) {
                 constexpr int k1 = decltype(kc)::value;
-                a[k1][q] = rot<R, DIR, q * k1>(u[k1]);
+                // Q = 2 and 4: the twiddles are folded into the second layer below
+                if constexpr (Q == 2 || Q == 4) a[k1][q] = u[k1];
+                else a[k1][q] = rot<R, DIR, q * k1>(u[k1]);
             });
         });
         sfor<0, P>([&](auto kc) {
             constexpr int k1 = decltype(kc)::value;
-            dft<Q, DIR>(a[k1]);
+            if constexpr (Q == 4) {
+                dft4_rot<R, DIR, k1>(a[k1]);
+            } else if constexpr (Q == 2) {
+                cx<T> s0, s1;
+                add_sub_rot<R, DIR, k1>(a[k1][0], a[k1][1], s0, s1);
+                a[k1][0] = s0;
+                a[k1][1] = s1;
+            } else {
+                dft<Q, DIR>(a[k1]);
+            }
             sfor<0, Q>([&](auto k2c) {
                 constexpr int k2 = decltype(k2c)::value;
                 x[k1 + P * k2] = a[k1][k2];
