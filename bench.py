@@ -49,14 +49,16 @@ def percentile(xs, q):
 
 
 def source_hash() -> str:
-    """Hash of every kernel and runtime source, to tie counter data to a build."""
+    """Hash of every kernel and runtime source and of the build script (its
+    compile flags), to tie counter data to a build."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, CSRC)
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    paths = [os.path.join(d, name) for name in sorted(os.listdir(d)) if name.endswith((".hip", ".h", ".cpp"))]
+    paths.append(os.path.join(ROOT, "paper_1106_0557_amd", "build.py"))
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
