@@ -630,98 +630,25 @@ __device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int 
     return zl;
 }
 
-// Z_CONV with compile-time geometry, persistent: workgroup b handles the tiles
-// b, b + gridDim.x, ...  The stored half of the next tile's line and its
-// spectrum values are loaded before the current tile's stores.  Vector loads and
-// stores retire in order, so waiting for those values never waits for the
-// stores, and the loads run under the current tile's transforms.  Every problem
-// of such a launch has the same line length and radices, hence the same stage
-// twiddles, which are staged once.
-template <typename T, int E, int K, int FIX>
-__global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zconv_kernel(const LaunchArgs args) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
-    constexpr int H = E / 2;
-    constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
-    constexpr int NB = FIX == 2 ? K : (E & -E) * K;
-    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, Z_CONV, NB);
-    constexpr int LDSW = TILE + 1;
-    using FFT_F = LineFFT<T, E, -1, false, NB, LDSW>;
-    using FFT_I = LineFFT<T, E, +1, false, NB, LDSW>;
-    static_assert(FIX == 2 || FIX == 3, "compile-time geometry only");
-
-    int bid = static_cast<int>(blockIdx.x);
-    if (bid >= args.nwg) return;
-    const int tid = threadIdx.x;
-    const int c = tid & (TILE - 1);
-    const int t = tid >> __builtin_ctz(TILE);
-    const AxisPlan &ax0 = args.p[0].plan->ax[2];
-    cx<T> *twl = lds + data_elems(false, E * NB, NB, TILE * NB, CSZ);
-    copy_to_lds<T>(twl, ax0.tw, ax0.ntw);  // visible after the first transform's leading barrier
-
-    // Spectrum values of a line: G~ is even in kz, so position t + NB*m reads
-    // octant index t + NB*m for m < E/2 and NB*(E - m) - t otherwise.
-    auto load_g = [](const ZLine<T> &zl, T *gv) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const uint32_t idx = m < H ? m : E - m - 1;
-            gv[m] = *reinterpret_cast<const gbl<T> *>(zl.g + ((m < H ? zl.glo : zl.ghi) + idx * zl.gstep));
-        }
-    };
-    ZLine<T> cur = z_line<T, E, NB, TILE>(args, bid, c, t);
-    cx<T> nxt[H];
-    T gnx[E];
-#pragma unroll
-    for (int m = 0; m < H; ++m) nxt[m] = cur.lane[m];
-    load_g(cur, gnx);
-    // Nothing outstanding when the loop is entered, as at the end of each pass
-    // through it (vmcnt 0, expcnt and lgkmcnt unconstrained).
-    __builtin_amdgcn_s_waitcnt(0x0f70);
-    for (;;) {
-        cx<T> v[E];
-        T gv[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            v[m] = m < H ? nxt[m] : cx<T>{T(0), T(0)};
-            gv[m] = gnx[m];
-        }
-        // The next tile's line and spectrum values are loaded before this tile's
-        // stores, and unconditionally (the last tile loads its own again; lanes
-        // without a line store out of range), so the compiler counts the same
-        // outstanding operations on every path and no wait covers the stores.
-        const int nbid = bid + static_cast<int>(gridDim.x);
-        const bool more = nbid < args.nwg;
-        const ZLine<T> fol = z_line<T, E, NB, TILE>(args, more ? nbid : bid, c, t);
-#pragma unroll
-        for (int m = 0; m < H; ++m) nxt[m] = fol.lane[m];
-        load_g(fol, gnx);
-        FFT_F::template run<K>(v, ax0, lds, LDSW, twl, c, t);
-#pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = scale(v[m], gv[m]);
-        FFT_I::template run<K>(v, ax0, lds, LDSW, twl, c, t);
-        // the out-of-range offset is chosen per element (a sum could wrap into range)
-#pragma unroll
-        for (int m = 0; m < H; ++m) {
-            const uint32_t off = static_cast<uint32_t>(cur.lane.lane) +
-                                 static_cast<uint32_t>(m) * static_cast<uint32_t>(cur.lane.step);
-            buffer_store<T>(v[m], cur.lane.base, cur.bytes, cur.active ? off : 0xfffffff0u);
-        }
-        if (!more) break;
-        cur = fol;
-        bid = nbid;
-    }
-}
-
 // Z_CONV for lines of 16, 32 or 64 threads (radices E, M, K with M*K = NB): each
 // line lies within one wavefront (wavefront w holds lines w*64/NB onwards), so
 // the stage exchanges stay inside the wavefront and need no workgroup barrier.
 // The tile's stored half is loaded with adjacent lanes on adjacent lines
 // (128-byte row segments) and transposed through each line's LDS row; the
 // results go back the same way.  The spectrum is stored kz-fastest for such
-// plans, so each line's values are read in contiguous runs.  PERSIST: the
-// workgroup walks tiles b, b + gridDim.x, ... and issues the next tile's loads
-// before the current tile's stores, as in zconv_kernel; otherwise it takes one
-// tile.
+// plans, so each line's values are read in contiguous runs.
+//
+// PERSIST: the workgroup walks tiles b, b + gridDim.x, ... and issues the next
+// tile's line and spectrum loads before the current tile's stores.  Vector
+// loads and stores retire in order, so a load issued after stores cannot be
+// waited for without waiting for them; issued first, the loads run under the
+// current tile's transforms and no wait covers the stores.  For the compiler's
+// wait counts to be exact, every load and store of a pass through the loop is
+// unconditional (the last tile loads its own line again; lanes without a line
+// store past the end of the array, which the buffer range check drops), the
+// loop is entered with nothing outstanding, and plan fields are read through
+// the constant address space (scalar loads; a vector load there would wait for
+// the previous tile's stores).  Otherwise the workgroup takes one tile.
 template <typename T, int E, int K, bool PERSIST>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zconv_wave_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -861,11 +788,12 @@ hipError_t launch_zconv_wave(const LaunchArgs &args, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// Where the persistent z convolution runs (PSPFFT_ZCONV_PERSIST: 0 never, 1
-// always, unset: where one workgroup fills a compute unit).  With two or more
-// workgroups per unit the hardware already overlaps one's memory traffic with
-// another's transforms, and its in-order dispatch keeps the tiles in flight
-// neighbours in memory, which long-lived workgroups drift away from.
+// Where the wavefront-owned z convolution runs persistently
+// (PSPFFT_ZCONV_PERSIST: 0 never, 1 always, unset: where one workgroup fills a
+// compute unit).  With two or more workgroups per unit the hardware already
+// overlaps one's memory traffic with another's transforms, and its in-order
+// dispatch keeps the tiles in flight neighbours in memory, which long-lived
+// workgroups drift away from.
 inline int zconv_persist_mode() {
     static int v = -2;
     if (v == -2) {
@@ -873,42 +801,6 @@ inline int zconv_persist_mode() {
         if (const char *e = std::getenv("PSPFFT_ZCONV_PERSIST")) v = std::atoi(e) != 0 ? 1 : 0;
     }
     return v;
-}
-
-// Launches the persistent z convolution and returns true where it is chosen;
-// *err receives the launch status.  The grid is what the device holds at once.
-template <typename T, int E, int K, int FIX>
-bool launch_zconv(const LaunchArgs &args, int block, size_t lds, hipStream_t stream, hipError_t *err) {
-    constexpr int kMaxDevices = 64;
-    static int per_cu[kMaxDevices] = {0}, cus[kMaxDevices] = {0};
-    auto fn = zconv_kernel<T, E, K, FIX>;
-    const int mode = zconv_persist_mode();
-    if (mode == 0) return false;
-    int dev = 0;
-    *err = hipGetDevice(&dev);
-    if (*err != hipSuccess) return true;
-    if (dev < 0 || dev >= kMaxDevices) {
-        *err = hipErrorInvalidDevice;
-        return true;
-    }
-    if (per_cu[dev] == 0) {
-        *err = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024);
-        if (*err != hipSuccess) return true;
-        int p = 0, c = 0;
-        *err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, fn, block, lds);
-        if (*err != hipSuccess) return true;
-        *err = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
-        if (*err != hipSuccess) return true;
-        per_cu[dev] = p > 0 ? p : 1;
-        cus[dev] = c > 0 ? c : 1;
-    }
-    if (mode < 0 && per_cu[dev] > 1) return false;
-    int grid = per_cu[dev] * cus[dev];
-    if (grid > args.nwg) grid = args.nwg;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, stream, args);
-    *err = hipGetLastError();
-    return true;
 }
 
 template <typename T, int E, int K, int MODE, int FIX>
@@ -935,10 +827,6 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
                 if (args.wave_z) return launch_zconv_wave<T, E, K>(args, stream);
             }
             if (args.wave_z) return hipErrorInvalidValue;  // a kz-fastest spectrum needs zconv_wave_kernel
-            if constexpr (FIX != 0) {
-                hipError_t e = hipSuccess;
-                if (launch_zconv<T, E, K, FIX>(args, block, lds, stream, &e)) return e;
-            }
             return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
         case Y_INV: return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
         case X_INV: return launch_kernel<T, E, K, X_INV, FIX>(args, grid, block, lds, stream);
