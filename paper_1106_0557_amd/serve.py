@@ -8,14 +8,15 @@ workspaces are pooled.  A request is admitted when its device footprint
 
 Scheduling is at pass granularity.  Each scheduler step issues, for every
 in-flight request, the next of its passes (five, or three for a plan that fuses
-the x and y transforms of each plane); requests at the same pass are grouped
-into one batched launch (``pspfft_pass_batched``), and the pass groups of a step
-go to separate streams so that different requests' work overlaps on the
-device.  A request admitted while others are in flight starts its first
-pass in the next step, so a solve never waits for a whole batch to finish.
-Steps are ordered by events: every stream of step k+1 waits for all of step k.
-Results do not depend on the mix: each problem is tiled the same way whatever
-shares its launch.
+the x and y transforms of each plane); requests of one mesh size at the same
+pass are grouped into one batched launch (``pspfft_pass_batched``), and the
+launches of a step go to different streams.  A launch waits (by events) only for
+the launches its own requests were last in, so small meshes move through their
+passes while a large mesh's pass runs beside them, and a step retires when its
+own launches are done, in whatever order steps finish.  A request admitted while
+others are in flight starts its first pass in the next step, so a solve never
+waits for a whole batch to finish.  Results do not depend on the mix: each
+problem is tiled the same way whatever shares its launch.
 
 The executor interface (plans and byte counts, workspace pool, output
 allocation, ``begin_step``/``run_pass``/``end_step`` and ``is_done``/``wait`` on
@@ -49,14 +50,18 @@ class Request:
     t_done: float = math.nan
     _ws: Any = None
     _ptrs: Any = None            # executor's cached launch arguments while admitted
+    _dep: Any = None             # executor's record of the launch this request was last in
 
     @property
     def latency(self) -> float:
         return self.t_done - self.arrival
 
 
+NUM_STREAMS = 8
+
+
 class GpuExecutor:
-    """Executor over the HIP library: plan cache, workspace pool, five streams."""
+    """Executor over the HIP library: plan cache, workspace pool, a pool of streams."""
 
     def __init__(self, dtype=None, device: int = 0):
         import torch
@@ -70,15 +75,17 @@ class GpuExecutor:
         self.plans: Dict[Any, Any] = {}
         self.pool: Dict[Any, List[Any]] = collections.defaultdict(list)
         # default priority streams only
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(NUM_PASSES)]
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(NUM_STREAMS)]
         # first work on a stream sets up its queue; do that now rather than
         # inside the first steps that happen to use it
         for s in self.streams:
             with torch.cuda.stream(s):
                 torch.zeros(1, device=f"cuda:{device}")
             s.synchronize()
-        self._last_step_event = None
-        self._used = []
+        self._step = 0                  # index of the step being built
+        self._pending: set = set()      # steps issued and not yet seen complete
+        self._launches = 0              # launches of the step being built
+        self._step_events: List[Any] = []
         self._events: List[Any] = []  # recycled events
         self._ws_bytes: Dict[Any, int] = {}  # workspace bytes per mesh
 
@@ -148,7 +155,8 @@ class GpuExecutor:
 
     # ------------------------------------------------------------ launches
     def begin_step(self) -> None:
-        self._used = []
+        self._launches = 0
+        self._step_events = []
 
     def _pointers(self, req: Request):
         """Launch arguments of an admitted request, checked once."""
@@ -158,48 +166,55 @@ class GpuExecutor:
         return plan.handle, req._ws.handle, req.S.data_ptr(), req.phi.data_ptr()
 
     def run_pass(self, p: int, reqs: Sequence[Request]) -> None:
-        # the k-th pass group of a step goes to stream k: a step with one group
-        # stays on the stream of the previous step and needs no cross-stream wait
-        s = self.streams[len(self._used)]
-        if self._last_step_event is not None:
-            s.wait_event(self._last_step_event)  # after everything of the previous step
-        self._used.append(s)
+        # the k-th launch of a step goes to stream k (mod the pool); it waits
+        # only for the launches its requests were last in, unless their steps
+        # are already known complete
+        s = self.streams[self._launches % len(self.streams)]
+        self._launches += 1
+        waited = set()
         cols = ([], [], [], [])
         for r in reqs:
+            if r._dep is not None:
+                ev, step = r._dep
+                if step in self._pending and id(ev) not in waited:
+                    waited.add(id(ev))
+                    s.wait_event(ev)  # takes the event as recorded now
             if r._ptrs is None:
                 r._ptrs = self._pointers(r)
             for c, v in zip(cols, r._ptrs):
                 c.append(v)
         self.ps.pass_batched_ptrs(p, cols[0], cols[1], cols[2], cols[3], s.cuda_stream)
+        ev = self._event()
+        ev.record(s)
+        self._step_events.append(ev)
+        for r in reqs:
+            r._dep = (ev, self._step)
 
     def _event(self):
         return self._events.pop() if self._events else self.torch.cuda.Event()
 
     def end_step(self):
-        cur = self._used[0]
-        for s in self._used[1:]:  # join the streams this step used
-            ev = self._event()
-            ev.record(s)
-            cur.wait_event(ev)  # the wait takes the event as recorded now, so it can be reused
-            self._events.append(ev)
-        ev = self._event()
-        ev.record(cur)
-        self._last_step_event = ev
-        return ev
+        """The step's token: its index and the events of its launches."""
+        token = (self._step, tuple(self._step_events))
+        self._pending.add(self._step)
+        self._step += 1
+        return token
 
     def release_token(self, token) -> None:
-        """A retired step's event goes back to the pool (later waits on it were
-        already enqueued)."""
-        if token is not self._last_step_event:
-            self._events.append(token)
+        """A retired step: its launches are complete, so no later launch needs
+        to wait on its events, which go back to the pool."""
+        step, events = token
+        self._pending.discard(step)
+        self._events.extend(events)
 
     @staticmethod
     def is_done(token) -> bool:
-        return token.query()
+        return all(ev.query() for ev in token[1])
 
     @staticmethod
     def wait(token) -> None:
-        token.synchronize()
+        for ev in token[1]:
+            ev.synchronize()
 
     def synchronize(self) -> None:
         self.torch.cuda.synchronize(self.device)
@@ -272,26 +287,37 @@ class Server:
             self.inflight.append(req)
 
     # -------------------------------------------------------------- stepping
+    def _finish(self, token, reqs) -> None:
+        release = getattr(self.ex, "release_token", None)
+        if release is not None:
+            release(token)
+        t = self.now()
+        for r in reqs:
+            r.done = True
+            r.t_done = t
+            self.ex.release(r, r._ws)  # back to the pool, still counted in `used`
+            r._ws = None
+            r._ptrs = None
+            r._dep = None
+            self.used -= self.ex.output_bytes(r)  # the output now belongs to the caller
+            self.finished.append(r)
+
     def _retire(self, block: bool = False) -> None:
+        """Retire every finished step, in whatever order they finish; with
+        ``block``, wait for the oldest one if none has."""
         while self.steps:
-            token, reqs = self.steps[0]
-            if not self.ex.is_done(token):
-                if not block:
-                    return
-                self.ex.wait(token)
-            self.steps.popleft()
-            release = getattr(self.ex, "release_token", None)
-            if release is not None:
-                release(token)
-            t = self.now()
-            for r in reqs:
-                r.done = True
-                r.t_done = t
-                self.ex.release(r, r._ws)  # back to the pool, still counted in `used`
-                r._ws = None
-                r._ptrs = None
-                self.used -= self.ex.output_bytes(r)  # the output now belongs to the caller
-                self.finished.append(r)
+            keep = collections.deque()
+            retired = False
+            for token, reqs in self.steps:
+                if self.ex.is_done(token):
+                    self._finish(token, reqs)
+                    retired = True
+                else:
+                    keep.append((token, reqs))
+            self.steps = keep
+            if retired or not block or not self.steps:
+                return
+            self.ex.wait(self.steps[0][0])
 
     def step(self) -> bool:
         """One scheduler iteration; returns False when there is nothing to do."""
@@ -301,14 +327,14 @@ class Server:
         self._admit()
         if not self.inflight:
             return bool(self.waiting) or bool(self.steps)
-        groups: Dict[int, List[Request]] = collections.defaultdict(list)
+        groups: Dict[Tuple[int, Tuple[int, int, int]], List[Request]] = collections.defaultdict(list)
         for r in self.inflight:
-            groups[r.next_pass].append(r)
+            groups[(r.next_pass, r.n)].append(r)
         self.ex.begin_step()
-        for p in sorted(groups):
-            self.ex.run_pass(p, groups[p])
+        for key in sorted(groups):
+            self.ex.run_pass(key[0], groups[key])
             self.launches += 1
-            self.max_batch = max(self.max_batch, len(groups[p]))
+            self.max_batch = max(self.max_batch, len(groups[key]))
         token = self.ex.end_step()
         completing = []
         still = []
