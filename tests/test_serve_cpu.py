@@ -181,6 +181,47 @@ def test_requests_join_while_others_are_in_flight():
     assert mixed
 
 
+class SizedExecutor(FakeExecutor):
+    """A step's token takes more polls when the step holds a large mesh."""
+
+    def __init__(self, slow_polls=40, **kw):
+        super().__init__(**kw)
+        self.slow_polls = slow_polls
+        self._big = False
+
+    def begin_step(self):
+        super().begin_step()
+        self._big = False
+
+    def run_pass(self, p, reqs):
+        super().run_pass(p, reqs)
+        self._big |= any(r.n[0] >= 64 for r in reqs)
+
+    def end_step(self):
+        return FakeToken(self.slow_polls if self._big else 0)
+
+
+def test_steps_retire_in_the_order_they_finish():
+    """A step of small meshes that finishes retires before an earlier step that
+    holds a large mesh's pass (the executor orders launches per request, not per
+    step), and launches group requests by pass and mesh size."""
+    ex = SizedExecutor(fused_sizes=(16,))
+    clock = itertools.count()
+    srv = Server(ex, budget_bytes=1 << 40, max_inflight=2, clock=lambda: next(clock) * 1e-3)
+    reqs = _reqs([64, 16, 16, 16, 16])
+    fin = srv.run_trace(reqs, realtime=False)
+    assert all(r.done and not r.rejected for r in fin)
+    big = reqs[0]
+    done_step = {i: max(s for s, _, r in ex.log if r == i) for i in range(len(reqs))}
+    later_small = [r for r in reqs[1:] if done_step[r.index] > done_step[0]]
+    assert later_small, "a small request completes in a step after the large one's last"
+    assert any(r.t_done < big.t_done for r in later_small)
+    # one launch per (pass, size): a step's log holds each request once
+    for s in set(x[0] for x in ex.log):
+        rs = [r for t, _, r in ex.log if t == s]
+        assert len(rs) == len(set(rs))
+
+
 def test_pool_reuse_and_trim():
     ex = FakeExecutor()
     srv = Server(ex, budget_bytes=1 << 40, max_inflight=2, max_steps_ahead=2)
