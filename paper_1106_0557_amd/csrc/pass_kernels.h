@@ -36,7 +36,7 @@ struct LineFFT {
     static constexpr int M = E & -E;  // radix of the middle stages
 
     // LDS layout: column passes keep (line c, position P) at P*ldsw + c with
-    // ldsw = tile + 1; row passes at c*ldsw + P + P/16 with ldsw = row_stride().
+    // ldsw = col_stride(); row passes at c*ldsw + P + P/16 with ldsw = row_stride().
     static __device__ __forceinline__ void gather(cx<T> *v, const cx<T> *lds, int ldsw_, int c, int t, int NB_) {
         const int NB = CNB ? CNB : NB_;
         const int ldsw = CLDSW ? CLDSW : ldsw_;
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr int CNB = FIX == 2 ? K : (FIX == 3 ? (E & -E) * K : 0);
     constexpr int FTILE = fix_tile(sizeof(T) == 4 ? 0 : 1, MODE, CNB);
     constexpr int CL = E * CNB;  // line length when compile-time
-    constexpr int CLDSW = FIX ? (ROW ? row_stride(CL, CNB, CSZ) : FTILE + 1) : 0;
+    constexpr int CLDSW = FIX ? (ROW ? row_stride(CL, CNB, CSZ) : col_stride(CL, FTILE, CSZ)) : 0;
     using FFT_F = LineFFT<T, E, -1, ROW, CNB, CLDSW>;
     using FFT_I = LineFFT<T, E, +1, ROW, CNB, CLDSW>;
 
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         c = tid & (tile - 1);
         t = tid >> __builtin_ctz(tile);
     }
-    const int ldsw = FIX ? CLDSW : (ROW ? row_stride(L, NB, CSZ) : tile + 1);
+    const int ldsw = FIX ? CLDSW : (ROW ? row_stride(L, NB, CSZ) : col_stride(L, tile, CSZ));
     cx<T> *twl = lds + (FIX ? data_elems(ROW, CL, CNB, FTILE * CNB, CSZ) : data_elems(ROW, L, NB, block, CSZ));
     copy_to_lds<T>(twl, ax.tw, ax.ntw);
 
