@@ -277,6 +277,9 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr int CLDSW = FIX ? (ROW ? row_stride(CL, CNB, CSZ) : col_stride(CL, FTILE, CSZ)) : 0;
     using FFT_F = LineFFT<T, E, -1, ROW, CNB, CLDSW>;
     using FFT_I = LineFFT<T, E, +1, ROW, CNB, CLDSW>;
+    // compile-time rows of at most 64 threads are consecutive lanes of one
+    // wavefront, as is their LDS row: their exchanges need no workgroup barrier
+    constexpr bool RW = ROW && FIX != 0 && CNB <= 64;
 
     // XCD-aware order: hardware hands consecutive workgroups to the 8 XCDs in
     // turn; renumber so that each XCD works through a contiguous range of the
@@ -349,7 +352,12 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 if (m < H && active) v[m] = fld[m];
                 else v[m] = cx<T>{T(0), T(0)};
             }
-            FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
+            if constexpr (RW) {
+                __syncthreads();  // twiddles visible
+                FFT_F::template run<K, false, true>(v, ax, lds, ldsw, twl, c, t);
+            } else {
+                FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
+            }
             // split: X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k]).
             // Partners U[n-k]: from the mirror lane of the row with compile-time
             // geometry, else through the row in LDS.
@@ -426,7 +434,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 v[m] = cx<T>{sm.x - ed.y, sm.y + ed.x};
             }
             // with the mirror lanes nothing of the row is in LDS yet: no leading barrier
-            FFT_I::template run<K, FIX == 0>(v, ax, lds, ldsw, twl, c, t);
+            FFT_I::template run<K, FIX == 0, RW>(v, ax, lds, ldsw, twl, c, t);
             if (active) {
 #pragma unroll
                 for (int m = 0; m < H; ++m) fld[m] = v[m];
