@@ -162,11 +162,14 @@ __host__ __device__ constexpr int max_block_for(int prec, int E) {
     return prec == 0 ? (E == 16 ? 1024 : (E <= 24 ? 512 : 256)) : (E == 16 ? 512 : 256);
 }
 
-// LDS bytes of the wavefront-owned z convolution for lines of length L = E*NB:
-// one row per line of the tile, then the stage twiddles.
-__host__ __device__ constexpr size_t wave_z_lds_bytes(int prec, int E, int NB) {
+// LDS bytes of the wavefront-owned column kernel of pass `mode` for lines of
+// length L = E*NB: one row per line of the tile, then the stage twiddles.
+__host__ __device__ constexpr size_t wave_lds_bytes(int prec, int mode, int E, int NB) {
     const int L = E * NB;
-    return static_cast<size_t>(fix_tile(prec, Z_CONV, NB) * wave_line_stride(L) + L - 1) * (prec == 0 ? 8 : 16);
+    return static_cast<size_t>(fix_tile(prec, mode, NB) * wave_line_stride(L) + L - 1) * (prec == 0 ? 8 : 16);
+}
+__host__ __device__ constexpr size_t wave_z_lds_bytes(int prec, int E, int NB) {
+    return wave_lds_bytes(prec, Z_CONV, E, NB);
 }
 
 // Fused plane kernels (x and y transforms of one z plane per workgroup) for

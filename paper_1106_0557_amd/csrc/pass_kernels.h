@@ -638,16 +638,58 @@ __device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int 
     return zl;
 }
 
-// Z_CONV for lines of 16, 32 or 64 threads (radices E, M, K with M*K = NB): each
-// line lies within one wavefront (wavefront w holds lines w*64/NB onwards), so
-// the stage exchanges stay inside the wavefront and need no workgroup barrier.
-// The tile's stored half is loaded with adjacent lanes on adjacent lines
-// (128-byte row segments) and transposed through each line's LDS row; the
-// results go back the same way.  The spectrum is stored kz-fastest for such
-// plans, so each line's values are read in contiguous runs.
+// One y line of a compile-time Y_FWD / Y_INV launch for lane (c, t) of the
+// tile that virtual workgroup `bid` handles: line (z, kx) has position y at
+// w_row(z, y) + kx; the Nyquist line of plane z is contiguous in Wn.  No
+// spectrum (g stays null).
+template <typename T, int NB, int TILE>
+__device__ __forceinline__ ZLine<T> y_line(const LaunchArgs &args, int bid, int c, int t) {
+    constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
+    int sgi = 0;
+    while (sgi + 1 < args.nseg && bid >= args.seg[sgi + 1].wg_begin) ++sgi;
+    const Segment &sg = args.seg[sgi];
+    int local = bid - sg.wg_begin;
+    const int member = local % sg.group;
+    local /= sg.group;
+    const ProbArg &pa = args.p[sg.first + member];
+    using cplan = const __attribute__((address_space(4))) DevPlan;
+    const auto &pl = *(cplan *)pa.plan;
+    const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
+    const bool nyq = local >= sg.wg_main;
+    if (nyq) local -= sg.wg_main;
+    const int g = local * TILE + c;
+    ZLine<T> yl;
+    if (!nyq) {
+        yl.active = g < nz * nx;
+        const int z = yl.active ? g / nx : 0;
+        const int kx = g - z * nx;
+        const size_t es = static_cast<size_t>(pl.zb) * nx;
+        const size_t lane_off = w_row(z, 0, ny, nx, pl.zb) + kx + static_cast<size_t>(t) * es;
+        yl.lane = line_ptr<T, true>(pa.W, yl.active ? lane_off : 0, NB * es, CSZ);
+        yl.bytes = static_cast<uint32_t>(static_cast<size_t>(nz) * 2 * ny * nx * CSZ);
+    } else {
+        yl.active = g < nz;
+        const size_t lane_off = static_cast<size_t>(g) * 2 * ny + t;
+        yl.lane = line_ptr<T, true>(pa.Wn, yl.active ? lane_off : 0, NB, CSZ);
+        yl.bytes = static_cast<uint32_t>(static_cast<size_t>(nz) * 2 * ny * CSZ);
+    }
+    yl.g = nullptr;
+    yl.glo = yl.ghi = yl.gstep = 0u;
+    return yl;
+}
+
+// Column passes (Y_FWD, Z_CONV, Y_INV) for lines of 16, 32 or 64 threads
+// (radices E, M, K with M*K = NB): each line lies within one wavefront
+// (wavefront w holds lines w*64/NB onwards), so the stage exchanges stay inside
+// the wavefront and need no workgroup barrier.  The tile's stored half (all of
+// it for Y_INV) is loaded with adjacent lanes on adjacent lines (128-byte row
+// segments) and transposed through each line's LDS row; the results (the
+// stored half, all of them for Y_FWD) go back the same way.  Z_CONV: the
+// spectrum is stored kz-fastest for such plans, so each line's values are read
+// in contiguous runs.
 //
 // PERSIST: the workgroup walks tiles b, b + gridDim.x, ... and issues the next
-// tile's line and spectrum loads before the current tile's stores.  Vector
+// tile's line (and spectrum) loads before the current tile's stores.  Vector
 // loads and stores retire in order, so a load issued after stores cannot be
 // waited for without waiting for them; issued first, the loads run under the
 // current tile's transforms and no wait covers the stores.  For the compiler's
@@ -657,16 +699,20 @@ __device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int 
 // loop is entered with nothing outstanding, and plan fields are read through
 // the constant address space (scalar loads; a vector load there would wait for
 // the previous tile's stores).  Otherwise the workgroup takes one tile.
-template <typename T, int E, int K, bool PERSIST>
-__global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zconv_wave_kernel(const LaunchArgs args) {
+template <typename T, int E, int K, int MODE, bool PERSIST>
+__global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) wave_col_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
+    static_assert(MODE == Y_FWD || MODE == Z_CONV || MODE == Y_INV, "column passes");
     constexpr int H = E / 2;
     constexpr int NB = (E & -E) * K;
     static_assert(NB == 16 || NB == 32 || NB == 64, "lines of 16, 32 or 64 threads");
     constexpr int L = E * NB;
-    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, Z_CONV, NB);
+    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, MODE, NB);
     constexpr int S = wave_line_stride(L);
+    constexpr int NLOAD = MODE == Y_INV ? E : H;   // forward transforms read the stored half
+    constexpr int NSTORE = MODE == Y_FWD ? E : H;  // inverse ones keep the first half
+    constexpr bool ZC = MODE == Z_CONV;
     using FFT_F = LineFFT<T, E, -1, true, NB, S>;
     using FFT_I = LineFFT<T, E, +1, true, NB, S>;
 
@@ -675,7 +721,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
     const int tid = threadIdx.x;
     const int cc = tid & (TILE - 1), tc = tid >> __builtin_ctz(TILE);  // adjacent lanes on adjacent lines
     const int cw = tid >> __builtin_ctz(NB), tw = tid & (NB - 1);       // line cw lies in one wavefront
-    const AxisPlan &ax0 = args.p[0].plan->ax[2];
+    const AxisPlan &ax0 = args.p[0].plan->ax[ZC ? 2 : 1];
     cx<T> *twl = lds + TILE * S;
     copy_to_lds<T>(twl, ax0.tw, ax0.ntw);  // published by the first barrier below
     // position P = t + NB*m of a line's row sits at P + P/16 = t + t/16 + m*(NB + NB/16)
@@ -683,56 +729,73 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
     cx<T> *rowc = lds + cc * S + tc + (tc >> 4);
     cx<T> *roww = lds + cw * S + tw + (tw >> 4);
 
-    auto load_g = [](const ZLine<T> &zl, T *gv) {
+    auto line = [&](int b) __attribute__((always_inline)) {
+        if constexpr (ZC) return z_line<T, E, NB, TILE>(args, b, cc, tc);
+        else return y_line<T, NB, TILE>(args, b, cc, tc);
+    };
+    auto load_g = [&](int b, T *gv) __attribute__((always_inline)) {
+        if constexpr (ZC) {
+            const ZLine<T> zl = z_line<T, E, NB, TILE, true>(args, b, cw, tw);
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const uint32_t idx = m < H ? m : E - m - 1;
-            gv[m] = *reinterpret_cast<const gbl<T> *>(zl.g + ((m < H ? zl.glo : zl.ghi) + idx * zl.gstep));
+            for (int m = 0; m < E; ++m) {
+                const uint32_t idx = m < H ? m : E - m - 1;
+                gv[m] = *reinterpret_cast<const gbl<T> *>(zl.g + ((m < H ? zl.glo : zl.ghi) + idx * zl.gstep));
+            }
         }
     };
-    ZLine<T> cur = z_line<T, E, NB, TILE>(args, bid, cc, tc);
-    T gnx[E];
-    {
-        cx<T> first[H];
+    ZLine<T> cur = line(bid);
+    T gnx[ZC ? E : 1];
+    if constexpr (sizeof(T) == 4) {
+        // the line first (loads retire in order: its rows can be written
+        // while the spectrum values are still in flight)
+        cx<T> first[NLOAD];
 #pragma unroll
-        for (int m = 0; m < H; ++m) first[m] = cur.lane[m];
-        load_g(z_line<T, E, NB, TILE, true>(args, bid, cw, tw), gnx);
+        for (int m = 0; m < NLOAD; ++m) first[m] = cur.lane[m];
+        load_g(bid, gnx);
 #pragma unroll
-        for (int m = 0; m < H; ++m) rowc[m * RM] = first[m];
+        for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = first[m];
+    } else {
+        // FP64: sixteen-byte values held there do not stay in registers
+        load_g(bid, gnx);
+#pragma unroll
+        for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = cur.lane[m];
     }
     if constexpr (PERSIST) __builtin_amdgcn_s_waitcnt(0x0f70);  // nothing outstanding on entry (vmcnt 0)
     for (;;) {
         __syncthreads();  // the tile is in the rows (and, first time, the twiddles)
         cx<T> v[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = m < H ? roww[m * RM] : cx<T>{T(0), T(0)};
-        FFT_F::template run<K, true, true>(v, ax0, lds, S, twl, cw, tw);
+        for (int m = 0; m < E; ++m) v[m] = m < NLOAD ? roww[m * RM] : cx<T>{T(0), T(0)};
+        if constexpr (MODE != Y_INV) FFT_F::template run<K, true, true>(v, ax0, lds, S, twl, cw, tw);
+        if constexpr (ZC) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = scale(v[m], gnx[m]);
-        // the next tile's line and spectrum values, before this tile's stores
+            for (int m = 0; m < E; ++m) v[m] = scale(v[m], gnx[m]);
+        }
+        // the next tile's line (and spectrum values), before this tile's stores
         const int nbid = bid + static_cast<int>(gridDim.x);
         const bool more = PERSIST && nbid < args.nwg;
         const int fbid = more ? nbid : bid;
-        // FP64: the line is loaded after this tile's stores (eight more 16-byte
+        // FP64: the line is loaded after this tile's stores (the extra 16-byte
         // values held across the inverse transform do not stay in registers)
         constexpr bool PF = PERSIST && sizeof(T) == 4;
         ZLine<T> fol = cur;
-        cx<T> nxt[PF ? H : 1];
+        cx<T> nxt[PF ? NLOAD : 1];
         if constexpr (PERSIST) {
-            fol = z_line<T, E, NB, TILE>(args, fbid, cc, tc);
+            fol = line(fbid);
             if constexpr (PF) {
 #pragma unroll
-                for (int m = 0; m < H; ++m) nxt[m] = fol.lane[m];
+                for (int m = 0; m < NLOAD; ++m) nxt[m] = fol.lane[m];
             }
-            load_g(z_line<T, E, NB, TILE, true>(args, fbid, cw, tw), gnx);
+            load_g(fbid, gnx);
         }
-        FFT_I::template run<K, true, true>(v, ax0, lds, S, twl, cw, tw);
+        (void)nxt;
+        if constexpr (MODE != Y_FWD) FFT_I::template run<K, true, true>(v, ax0, lds, S, twl, cw, tw);
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int m = 0; m < H; ++m) roww[m * RM] = v[m];
+        for (int m = 0; m < NSTORE; ++m) roww[m * RM] = v[m];
         __syncthreads();  // results are in the rows
 #pragma unroll
-        for (int m = 0; m < H; ++m) {
+        for (int m = 0; m < NSTORE; ++m) {
             const uint32_t off = static_cast<uint32_t>(cur.lane.lane) +
                                  static_cast<uint32_t>(m) * static_cast<uint32_t>(cur.lane.step);
             buffer_store<T>(rowc[m * RM], cur.lane.base, cur.bytes, cur.active ? off : 0xfffffff0u);
@@ -741,10 +804,10 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
         __syncthreads();  // the rows have been read
         if constexpr (PF) {
 #pragma unroll
-            for (int m = 0; m < H; ++m) rowc[m * RM] = nxt[m];
+            for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = nxt[m];
         } else {
 #pragma unroll
-            for (int m = 0; m < H; ++m) rowc[m * RM] = fol.lane[m];
+            for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = fol.lane[m];
         }
         cur = fol;
         bid = nbid;
@@ -753,20 +816,19 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) zc
 
 inline int zconv_persist_mode();
 
-// The wavefront-owned z convolution: persistent where one workgroup fills a
+// The wavefront-owned column kernel: persistent where one workgroup fills a
 // compute unit (zconv_persist_mode), otherwise one tile per workgroup.
-template <typename T, int E, int K>
-hipError_t launch_zconv_wave(const LaunchArgs &args, hipStream_t stream) {
+template <typename T, int E, int K, int MODE>
+hipError_t launch_wave_col(const LaunchArgs &args, hipStream_t stream) {
     constexpr int kMaxDevices = 64;
-    constexpr int NB = (E & -E) * K, L = E * NB;
-    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, Z_CONV, NB);
-    constexpr int block = TILE * NB;
-    constexpr size_t lds = wave_z_lds_bytes(sizeof(T) == 4 ? 0 : 1, E, NB);
-    static_assert(lds == static_cast<size_t>(TILE * wave_line_stride(L) + L - 1) * sizeof(cx<T>), "layout");
+    constexpr int prec = sizeof(T) == 4 ? 0 : 1;
+    constexpr int NB = (E & -E) * K;
+    constexpr int block = fix_tile(prec, MODE, NB) * NB;
+    constexpr size_t lds = wave_lds_bytes(prec, MODE, E, NB);
     static_assert(lds <= 160 * 1024, "tile rows and twiddles fit the LDS");
     static int per_cu[kMaxDevices] = {0}, cus[kMaxDevices] = {0};
-    auto fp = zconv_wave_kernel<T, E, K, true>;
-    auto fo = zconv_wave_kernel<T, E, K, false>;
+    auto fp = wave_col_kernel<T, E, K, MODE, true>;
+    auto fo = wave_col_kernel<T, E, K, MODE, false>;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -796,7 +858,21 @@ hipError_t launch_zconv_wave(const LaunchArgs &args, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// Where the wavefront-owned z convolution runs persistently
+// The y passes take wavefront-owned lines (three stages, 32 or 64 threads per
+// line) where the column kernel's tile needs more LDS than this, so that a CU
+// holds only one of its workgroups (PSPFFT_WAVE_Y_LDS overrides, in bytes;
+// 0 always).  Measured, with two or more per CU the column kernel is as fast.
+inline size_t wave_y_min_lds() {
+    static long v = -1;
+    if (v < 0) {
+        long x = 80 * 1024;
+        if (const char *e = std::getenv("PSPFFT_WAVE_Y_LDS")) x = std::atol(e);
+        v = x >= 0 ? x : 80 * 1024;
+    }
+    return static_cast<size_t>(v);
+}
+
+// Where the wavefront-owned column kernel runs persistently
 // (PSPFFT_ZCONV_PERSIST: 0 never, 1 always, unset: where one workgroup fills a
 // compute unit).  With two or more workgroups per unit the hardware already
 // overlaps one's memory traffic with another's transforms, and its in-order
@@ -829,14 +905,22 @@ template <typename T, int E, int K, int FIX>
 hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
     switch (mode) {
         case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
-        case Y_FWD: return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
+        case Y_FWD:
+            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64)) {
+                if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_FWD>(args, stream);
+            }
+            return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
         case Z_CONV:
             if constexpr (FIX == 3 && ((E & -E) * K == 16 || (E & -E) * K == 32 || (E & -E) * K == 64)) {
-                if (args.wave_z) return launch_zconv_wave<T, E, K>(args, stream);
+                if (args.wave_z) return launch_wave_col<T, E, K, Z_CONV>(args, stream);
             }
             if (args.wave_z) return hipErrorInvalidValue;  // a kz-fastest spectrum needs zconv_wave_kernel
             return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
-        case Y_INV: return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
+        case Y_INV:
+            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64)) {
+                if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_INV>(args, stream);
+            }
+            return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
         case X_INV: return launch_kernel<T, E, K, X_INV, FIX>(args, grid, block, lds, stream);
         default: return hipErrorInvalidValue;
     }
