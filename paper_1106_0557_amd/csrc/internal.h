@@ -145,17 +145,11 @@ __host__ __device__ constexpr int default_tile(int prec, bool row) {
     return row ? (prec == 0 ? 32 : 16) : (prec == 0 ? 16 : 8);
 }
 
-#ifndef PSPFFT_ZCONV_BLOCK_CAP
-#define PSPFFT_ZCONV_BLOCK_CAP 1024
-#endif
-// Lines per workgroup of pass `mode` for lines of nb threads: the default tile,
-// except that z convolution workgroups stay at or below PSPFFT_ZCONV_BLOCK_CAP
-// threads.
-__host__ __device__ constexpr int fix_tile(int prec, int mode, int nb) {
-    int t = default_tile(prec, mode == X_FWD || mode == X_INV);
-    if (mode == Z_CONV && nb > 0)
-        while (t > 1 && t * nb > PSPFFT_ZCONV_BLOCK_CAP) t /= 2;
-    return t;
+// Lines per workgroup of pass `mode` (lines of nb threads): the default tile.
+// Measured, smaller z-pass tiles (more workgroups per CU, 64- or 32-byte row
+// segments) lose at every size.
+__host__ __device__ constexpr int fix_tile(int prec, int mode, int /*nb*/) {
+    return default_tile(prec, mode == X_FWD || mode == X_INV);
 }
 
 __host__ __device__ constexpr int max_block_for(int prec, int E) {
