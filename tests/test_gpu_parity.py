@@ -196,7 +196,8 @@ def test_solve_matches_oracle(n):
 # (24*8*4), each kept within one wavefront, 384 (24*8*2), 288 (36*4*2), 160
 # (20*4*2); x rows of 512 and 384.
 THREE_STAGE = [(16, 8, 256), (16, 8, 512), (16, 8, 384), (16, 8, 192), (16, 8, 288), (16, 512, 8),
-               (16, 384, 8), (16, 192, 8), (16, 144, 8), (20, 80, 160), (512, 8, 8), (384, 8, 8)]
+               (16, 384, 8), (16, 192, 8), (16, 144, 8), (20, 80, 160), (512, 8, 8), (384, 8, 8),
+               (16, 384, 288)]
 
 
 @pytest.mark.parametrize("n", THREE_STAGE)
