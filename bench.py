@@ -260,6 +260,48 @@ def main():
         torch.cuda.empty_cache()
         log(f"[bench] large: {large}")
 
+    # ------------------------------ config 3: 64 mixed-size sources, one batch
+    config3 = None
+    if not args.no_serve:
+        import paper_1106_0557_amd.sources as srcmod
+
+        log("[bench] config 3: 64 sources of sizes {32..128}^3 in one pspfft_solve_batched call")
+        batch = srcmod.config3(device="cuda")
+        plans3, ws3, S3, P3 = {}, [], [], []
+        for nn, src in batch:
+            if nn not in plans3:
+                plans3[nn] = ps.Plan(nn, nn, nn, h=1.0 / nn, dtype=torch.float32)
+            ws3.append(plans3[nn].workspace())
+            S3.append(src.to(torch.float32).contiguous())
+            P3.append(torch.empty_like(S3[-1]))
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            for _ in range(3):
+                ps.solve_batched(ws3, S3, P3, stream=st)
+            st.synchronize()
+            reps = 30
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                ps.solve_batched(ws3, S3, P3, stream=st)
+            e1.record(st)
+            e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        alg3 = sum(algorithmic_bytes(nn, 4) for nn, _ in batch)
+        counts = {}
+        for nn, _ in batch:
+            counts[nn] = counts.get(nn, 0) + 1
+        config3 = {"problems": len(batch), "sizes": {str(k): v for k, v in sorted(counts.items())},
+                   "ms_per_batch": round(ms, 4), "solves_per_s": round(len(batch) / ms * 1e3, 1),
+                   "effective_GBps": round(alg3 / ms / 1e6, 1)}
+        log(f"[bench] config 3: {config3}")
+        for w in ws3:
+            w.close()
+        for pl3 in plans3.values():
+            pl3.close()
+        del S3, P3, batch
+        torch.cuda.empty_cache()
+
     # ----------------------------------------------- serving loop (Poisson)
     serve = None
     if not args.no_serve:
@@ -344,6 +386,7 @@ def main():
         "cpu_baseline": cpu,
         "served": serve,
         "single_large_solve": large,
+        "config3_batched": config3,
         "kernel_source_hash": source_hash(),
     }
     print(json.dumps(result), flush=True)
