@@ -156,6 +156,24 @@ __host__ __device__ constexpr int max_block_for(int prec, int E) {
     return prec == 0 ? (E == 16 ? 1024 : (E <= 24 ? 512 : 256)) : (E == 16 ? 512 : 256);
 }
 
+// Lines per workgroup of a line-pass launch (pass_kernel) for lines of nb
+// threads in radix family E: the default tile, halved while the workgroup
+// exceeds the family's largest or its LDS (data, stage twiddles and, for rows,
+// the split factors) exceeds 160 KB.  Long lines thus keep compile-time geometry
+// with a smaller tile.
+__host__ __device__ constexpr int pass_tile(int prec, int mode, int E, int nb) {
+    const bool row = mode == X_FWD || mode == X_INV;
+    const int L = E * nb, csz = prec == 0 ? 8 : 16;
+    int t = default_tile(prec, row);
+    if (nb <= 0) return t;  // run-time geometry
+    while (t > 1) {
+        const long elems = static_cast<long>(data_elems(row, L, nb, t * nb, csz)) + (L - 1) + (row ? L : 0);
+        if (static_cast<long>(t) * nb <= max_block_for(prec, E) && elems * csz <= 160 * 1024) break;
+        t /= 2;
+    }
+    return t;
+}
+
 // LDS bytes of the wavefront-owned column kernel of pass `mode` for lines of
 // length L = E*NB: one row per line of the tile, then the stage twiddles.
 __host__ __device__ constexpr size_t wave_lds_bytes(int prec, int mode, int E, int NB) {

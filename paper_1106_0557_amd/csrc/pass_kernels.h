@@ -260,10 +260,11 @@ __device__ __forceinline__ LinePtr<T, OFF32> line_ptr(const void *base, size_t l
     return LinePtr<T, OFF32>{const_cast<char *>(static_cast<const char *>(base)), lane_elems * esz, step_elems * esz};
 }
 
-// FIX (2 or 3): every problem of the launch has lines of that many stages with
-// radices E, (M,) K, the workgroup holds the default number of lines, so the
-// geometry is compile-time, and every array is below 4 GB, so addresses use
-// 32-bit lane offsets.  FIX = 0: geometry from the plan at run time.
+// FIX & 3 (2 or 3): every problem of the launch has lines of that many stages
+// with radices E, (M,) K and the workgroup holds the default number of lines, so
+// the geometry is compile-time.  FIX & 4 clear: every array is below 4 GB, so
+// addresses use 32-bit lane offsets; set (FIX = 6 or 7): 64-bit addresses.
+// FIX = 0: geometry from the plan at run time, 64-bit addresses.
 template <typename T, int E, int K, int MODE, int FIX>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pass_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -271,15 +272,18 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr bool ROW = (MODE == X_FWD || MODE == X_INV);
     constexpr int H = E / 2;  // registers m < H hold the first half of the line
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
-    constexpr int CNB = FIX == 2 ? K : (FIX == 3 ? (E & -E) * K : 0);
-    constexpr int FTILE = fix_tile(sizeof(T) == 4 ? 0 : 1, MODE, CNB);
+    constexpr int ST = FIX & 3;  // compile-time stages (0: run-time geometry)
+    constexpr bool OFF32 = ST != 0 && (FIX & 4) == 0;
+    constexpr int CNB = ST == 2 ? K : (ST == 3 ? (E & -E) * K : 0);
+    constexpr int FTILE = pass_tile(sizeof(T) == 4 ? 0 : 1, MODE, E, CNB);
     constexpr int CL = E * CNB;  // line length when compile-time
-    constexpr int CLDSW = FIX ? (ROW ? row_stride(CL, CNB, CSZ) : col_stride(CL, FTILE, CSZ)) : 0;
+    constexpr int CLDSW = ST ? (ROW ? row_stride(CL, CNB, CSZ) : col_stride(CL, FTILE, CSZ)) : 0;
     using FFT_F = LineFFT<T, E, -1, ROW, CNB, CLDSW>;
     using FFT_I = LineFFT<T, E, +1, ROW, CNB, CLDSW>;
     // compile-time rows of at most 64 threads are consecutive lanes of one
-    // wavefront, as is their LDS row: their exchanges need no workgroup barrier
-    constexpr bool RW = ROW && FIX != 0 && CNB <= 64;
+    // wavefront, as is their LDS row: their exchanges need no workgroup barrier,
+    // and the partners of the split step come from the mirror lane
+    constexpr bool RW = ROW && ST != 0 && CNB <= 64;
 
     // XCD-aware order: hardware hands consecutive workgroups to the 8 XCDs in
     // turn; renumber so that each XCD works through a contiguous range of the
@@ -306,10 +310,10 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr int axis = ROW ? 0 : (MODE == Z_CONV ? 2 : 1);
     const AxisPlan &ax = pl.ax[axis];
     const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
-    const int NB = FIX ? CNB : ax.NB;
-    const int L = FIX ? CL : ax.L;
-    const int block = FIX ? FTILE * CNB : static_cast<int>(blockDim.x);
-    const int tile = FIX ? FTILE : block / NB;  // lines per workgroup (power of two)
+    const int NB = ST ? CNB : ax.NB;
+    const int L = ST ? CL : ax.L;
+    const int block = ST ? FTILE * CNB : static_cast<int>(blockDim.x);
+    const int tile = ST ? FTILE : block / NB;  // lines per workgroup (power of two)
     const int tid = threadIdx.x;
     int c, t;
     if constexpr (ROW) {  // rows are contiguous in memory: consecutive lanes walk along a row
@@ -319,8 +323,8 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         c = tid & (tile - 1);
         t = tid >> __builtin_ctz(tile);
     }
-    const int ldsw = FIX ? CLDSW : (ROW ? row_stride(L, NB, CSZ) : col_stride(L, tile, CSZ));
-    cx<T> *twl = lds + (FIX ? data_elems(ROW, CL, CNB, FTILE * CNB, CSZ) : data_elems(ROW, L, NB, block, CSZ));
+    const int ldsw = ST ? CLDSW : (ROW ? row_stride(L, NB, CSZ) : col_stride(L, tile, CSZ));
+    cx<T> *twl = lds + (ST ? data_elems(ROW, CL, CNB, FTILE * CNB, CSZ) : data_elems(ROW, L, NB, block, CSZ));
     copy_to_lds<T>(twl, ax.tw, ax.ntw);
 
     const bool nyq = local >= sg.wg_main;
@@ -343,9 +347,9 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         const size_t wrow = w_row(z, y, ny, nx, pl.zb);  // row start in W (elements)
         cx<T> *wnyq = Wn + static_cast<size_t>(z) * 2 * ny + y;
         // thread t's positions t + NB*m of row g of S / Phi (pairs of reals) and of W
-        const auto fld = line_ptr<T, FIX != 0>(MODE == X_FWD ? pa.S : pa.Phi,
+        const auto fld = line_ptr<T, OFF32>(MODE == X_FWD ? pa.S : pa.Phi,
                                           static_cast<size_t>(active ? g : 0) * nx / 2 + t, NB, CSZ);
-        const auto wl = line_ptr<T, FIX != 0>(W, wrow + t, NB, CSZ);
+        const auto wl = line_ptr<T, OFF32>(W, wrow + t, NB, CSZ);
         if constexpr (MODE == X_FWD) {
 #pragma unroll
             for (int m = 0; m < E; ++m) {
@@ -362,7 +366,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             // Partners U[n-k]: from the mirror lane of the row with compile-time
             // geometry, else through the row in LDS.
             cx<T> wp[E];
-            if constexpr (FIX) {
+            if constexpr (RW) {
                 mirror_partners<T, E, CNB>(v, wp, t, tid & 63);
             } else {
                 __syncthreads();
@@ -405,7 +409,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             if (active) xn = *wnyq;
             // partners X[n-k] (X[n] for k = 0): mirror lane, or through the row in LDS
             cx<T> wp[E];
-            if constexpr (FIX) {
+            if constexpr (RW) {
                 mirror_partners<T, E, CNB>(v, wp, t, tid & 63);
                 __syncthreads();  // post table and twiddles visible
             } else {
@@ -434,7 +438,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 v[m] = cx<T>{sm.x - ed.y, sm.y + ed.x};
             }
             // with the mirror lanes nothing of the row is in LDS yet: no leading barrier
-            FFT_I::template run<K, FIX == 0, RW>(v, ax, lds, ldsw, twl, c, t);
+            FFT_I::template run<K, !RW, RW>(v, ax, lds, ldsw, twl, c, t);
             if (active) {
 #pragma unroll
                 for (int m = 0; m < H; ++m) fld[m] = v[m];
@@ -493,7 +497,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
             const int sh = __builtin_ctz(static_cast<unsigned>(zb));
             lane_off = base + (static_cast<size_t>(t >> sh) * 2 * ny * zb + (t & (zb - 1))) * nx;
         }
-        const auto lane = line_ptr<T, FIX != 0>(arr, active ? lane_off : 0, static_cast<size_t>(NB) * es, CSZ);
+        const auto lane = line_ptr<T, OFF32>(arr, active ? lane_off : 0, static_cast<size_t>(NB) * es, CSZ);
         // Forward transforms read only the stored half (m < H); inverse ones
         // read the whole line.
         constexpr int nload = (MODE == Y_INV) ? E : H;
@@ -522,7 +526,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 const size_t idx = m < H ? m : E - m - 1;
-                if constexpr (FIX) {
+                if constexpr (OFF32) {
                     const uint32_t o = static_cast<uint32_t>(m < H ? glane : ghane) +
                                        static_cast<uint32_t>(idx) * static_cast<uint32_t>(gstep);
                     gv[m] = *reinterpret_cast<const gbl<T> *>(gbase + o);
@@ -901,23 +905,33 @@ hipError_t launch_kernel(const LaunchArgs &args, int grid, int block, size_t lds
     return hipGetLastError();
 }
 
+// The wavefront-owned column kernel exists for three-stage lines of 16, 32 or 64
+// threads whose default tile fits the family's largest workgroup and the LDS.
+template <typename T, int E, int K, int MODE>
+constexpr bool wave_col_fits() {
+    constexpr int prec = sizeof(T) == 4 ? 0 : 1;
+    constexpr int NB = (E & -E) * K;
+    return (NB == 16 || NB == 32 || NB == 64) && fix_tile(prec, MODE, NB) * NB <= max_block_for(prec, E) &&
+           wave_lds_bytes(prec, MODE, E, NB) <= 160 * 1024;
+}
+
 template <typename T, int E, int K, int FIX>
 hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
     switch (mode) {
         case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
         case Y_FWD:
-            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64)) {
+            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64) && wave_col_fits<T, E, K, Y_FWD>()) {
                 if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_FWD>(args, stream);
             }
             return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
         case Z_CONV:
-            if constexpr (FIX == 3 && ((E & -E) * K == 16 || (E & -E) * K == 32 || (E & -E) * K == 64)) {
+            if constexpr (FIX == 3 && wave_col_fits<T, E, K, Z_CONV>()) {
                 if (args.wave_z) return launch_wave_col<T, E, K, Z_CONV>(args, stream);
             }
             if (args.wave_z) return hipErrorInvalidValue;  // a kz-fastest spectrum needs zconv_wave_kernel
             return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
         case Y_INV:
-            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64)) {
+            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64) && wave_col_fits<T, E, K, Y_INV>()) {
                 if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_INV>(args, stream);
             }
             return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
@@ -926,9 +940,10 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
     }
 }
 
-// fix: 0 (run-time geometry), 2 or 3 (compile-time lines of that many stages).
-// Three-stage instances exist where a default-tile workgroup of M*K threads per
-// line fits the family's largest workgroup.
+// fix: 0 (run-time geometry), 2 or 3 (compile-time lines of that many stages),
+// 6 or 7 (the same with 64-bit addresses, for arrays of 4 GB or more).
+// Three-stage instances exist where a workgroup of pass_tile() lines of M*K
+// threads fits the family's largest workgroup.
 template <typename T, int E, int K>
 hipError_t launch_fix(int mode, int fix, const LaunchArgs &args, int grid, int block, size_t lds,
                       hipStream_t stream) {
@@ -936,8 +951,10 @@ hipError_t launch_fix(int mode, int fix, const LaunchArgs &args, int grid, int b
     constexpr int M = E & -E;
     if constexpr (K > 1) {
         if (fix == 2) return launch_mode<T, E, K, 2>(mode, args, grid, block, lds, stream);
-        if constexpr (fix_tile(prec, Y_FWD, M * K) * M * K <= max_block_for(prec, E)) {
+        if (fix == 6) return launch_mode<T, E, K, 6>(mode, args, grid, block, lds, stream);
+        if constexpr (pass_tile(prec, Y_FWD, E, M * K) * M * K <= max_block_for(prec, E)) {
             if (fix == 3) return launch_mode<T, E, K, 3>(mode, args, grid, block, lds, stream);
+            if (fix == 7) return launch_mode<T, E, K, 7>(mode, args, grid, block, lds, stream);
         }
     }
     if (fix != 0) return hipErrorInvalidValue;

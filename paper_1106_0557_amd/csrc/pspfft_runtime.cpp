@@ -338,7 +338,7 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
             for (size_t j = c0; j < c1; ++j) nbmax = std::max(nbmax, plans[idx[j]]->host.ax[axis].NB);
             // (a kz-fastest spectrum needs the compile-time tile: no override)
             const int tile_target = gz ? pspfft::fix_tile(prec, mode, nbmax)
-                                       : line_tile(mode, pspfft::fix_tile(prec, mode, nbmax));
+                                       : line_tile(mode, pspfft::pass_tile(prec, mode, E, nbmax));
             for (size_t j = c0; j < c1; ++j) block = std::max(block, tile_target * plans[idx[j]]->host.ax[axis].NB);
             block = std::min(std::max(block, 64), bmax);
             auto lds_need = [&](int blk) {
@@ -396,8 +396,8 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
             const long align = args.xcd_remap == 1 ? 8 : (args.xcd_remap == 2 ? 64 : 1);
             const int grid = static_cast<int>((wg + align - 1) / align * align);
             // compile-time geometry when every line has two stages (radices E, K)
-            // or three (E, M, K), the workgroup holds the default number of lines,
-            // and every array is below 4 GB (32-bit offsets)
+            // or three (E, M, K) and the workgroup holds the default number of
+            // lines; 32-bit offsets when every array is below 4 GB (else fix + 4)
             const int M = E & -E;
             int fix = 0;
             if (K > 1) {
@@ -405,12 +405,17 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
                 if (a0.nst == 2) fix = 2;
                 else if (a0.nst == 3 && a0.R[1] == M) fix = 3;
                 const int cnb = fix == 2 ? K : M * K;
-                if (fix && block != pspfft::fix_tile(prec, mode, cnb) * cnb) fix = 0;
-                if (fix == 3 && pspfft::fix_tile(prec, mode, cnb) * cnb > pspfft::max_block_for(prec, E)) fix = 0;
+                if (fix && !gz && block != pspfft::pass_tile(prec, mode, E, cnb) * cnb) fix = 0;
+                if (fix && gz && block != pspfft::fix_tile(prec, mode, cnb) * cnb) fix = 0;
+                if (fix == 3 && pspfft::pass_tile(prec, pspfft::Y_FWD, E, cnb) * cnb > pspfft::max_block_for(prec, E))
+                    fix = 0;
+                bool wide = false;
                 for (size_t j = c0; j < c1 && fix; ++j) {
                     const AxisPlan &ax = plans[idx[j]]->host.ax[axis];
-                    if (ax.nst != a0.nst || ax.NB != cnb || !arrays_below_4gb(plans[idx[j]])) fix = 0;
+                    if (ax.nst != a0.nst || ax.NB != cnb) fix = 0;
+                    if (!arrays_below_4gb(plans[idx[j]])) wide = true;
                 }
+                if (fix && wide) fix += 4;
             }
             if (gz && fix != 3) return PSPFFT_ERR_UNSUPPORTED_SIZE;  // only zconv_wave_kernel reads that layout
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "

@@ -220,6 +220,28 @@ def test_three_stage_lines_match_oracle(n):
     assert r32["rel_l2"] <= FP32_TOL
 
 
+# Long lines whose default tile does not fit (the workgroup limit of the family
+# or the LDS), so their compile-time geometry takes a smaller tile: y and z lines
+# of 1536 (24*8*8) and 2048 (16*16*8, lines of 128 threads, two wavefronts), x
+# rows of 768 (24*8*4), 1024 (16*16*4) and 2048 (16*16*8, whose split-step
+# partners go through LDS rather than the mirror lane).
+LONG_LINES = [(16, 768, 8), (16, 8, 768), (768, 8, 8), (16, 1024, 8), (16, 8, 1024), (1024, 8, 8), (2048, 8, 8)]
+
+
+@pytest.mark.parametrize("n", LONG_LINES)
+def test_long_lines_match_oracle(n):
+    say(f"[long lines] n={n}")
+    h = (0.02, 0.03, 0.025)
+    S = sources.random_field(n, seed=sum(n) + 3).numpy()
+    ref = oracle.solve_fft(S, h)
+    got64 = gpu_solve(n, h, S, torch.float64)
+    got32 = gpu_solve(n, h, S, torch.float32)
+    r64, r32 = norms.report(got64, ref), norms.report(got32, ref)
+    say(f"  fp64 {r64}\n  fp32 {r32}")
+    assert r64["rel_l2"] <= FP64_TOL and r64["rel_max"] <= FP64_TOL
+    assert r32["rel_l2"] <= FP32_TOL
+
+
 def test_zero_source_gives_zero_potential():
     say("[zero source]")
     n = (24, 16, 20)
@@ -335,3 +357,50 @@ def test_config5_n512_sampled_direct_sum(dtype):
     err = np.abs(got - want).max() / np.abs(want).max()
     say(f"  sampled rel max err {err:.3e}")
     assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+def test_config5_fp64_and_fp32_agree_on_every_cell():
+    """The 512^3 solve in both precisions: the FP64 workspace passes 4 GB (64-bit
+    addressing), the FP32 one does not; the two potentials agree to the FP32
+    tolerance over the whole field."""
+    from paper_1106_0557_amd import Plan, workspace_bytes
+
+    say("[config5] n=512 fp64 vs fp32, whole field")
+    n, h, S = sources.config5(device="cuda")
+    assert workspace_bytes(n, n, n, torch.float64) >= 1 << 32 > workspace_bytes(n, n, n, torch.float32)
+    out = {}
+    for dt in (torch.float64, torch.float32):
+        plan = Plan(n, n, n, h=h, dtype=dt)
+        out[dt] = plan.solve(S.to(dt)).double()
+        torch.cuda.synchronize()
+        plan.close()
+    d = (torch.linalg.vector_norm(out[torch.float32] - out[torch.float64])
+         / torch.linalg.vector_norm(out[torch.float64])).item()
+    say(f"  rel l2 {d:.3e}")
+    assert d <= FP32_TOL
+
+
+def test_fp32_arrays_above_4gb_sampled_direct_sum():
+    """An FP32 mesh whose workspace passes 4 GB (64-bit addressing), with x rows of
+    768 = 24*8*4, y lines of 1536 = 24*8*8 and z lines of 1024 = 16*16*4, checked
+    at sampled targets by the direct sum."""
+    from paper_1106_0557_amd import Plan, workspace_bytes
+
+    n = (768, 768, 512)
+    h = (0.011, 0.009, 0.013)
+    say(f"[above_4gb] n={n} fp32")
+    assert workspace_bytes(*n, torch.float32) >= 1 << 32
+    S = sources.random_field(n, seed=57) + 1.0
+    size = n[0] * n[1] * n[2]
+    rng = np.random.default_rng(57)
+    targets = np.concatenate([np.unique(rng.integers(0, size, size=24)), [0, size - 1, size // 2 + n[0] // 2]])
+    want = oracle.direct(S.numpy(), h, targets)
+    plan = Plan(*n, h=h, dtype=torch.float32)
+    phi = plan.solve(S.to("cuda", torch.float32))
+    torch.cuda.synchronize()
+    got = phi.reshape(-1)[torch.from_numpy(targets).cuda()].double().cpu().numpy()
+    plan.close()
+    del phi
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say(f"  sampled rel max err {err:.3e}")
+    assert err <= FP32_TOL
