@@ -818,6 +818,226 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) wa
     }
 }
 
+// ------------------------------------------------- persistent column passes --
+// Column passes (Y_FWD, Z_CONV, Y_INV) with compile-time lines where one
+// workgroup of the column kernel fills a compute unit (long lines; FP64 from
+// 1024 points): the workgroup walks tiles b, b + gridDim.x, ... and loads the
+// next tile's line (and spectrum values) after the current tile's forward
+// transform and before its stores, so those loads run under the rest of the
+// work and no wait covers the stores (loads and stores retire in order).  For
+// the compiler's wait counts to be exact every load and store of the loop is
+// unconditional: a lane past the last line of its set takes that line again
+// (the same values go to the same addresses), the last tile prefetches itself,
+// and the loop is entered with nothing outstanding.
+template <typename T, bool OFF32>
+struct ColLine {
+    LinePtr<T, OFF32> lane;  // positions t + NB*m of the line in W (or Wn)
+    const char *g;           // z: spectrum octant (G, or Gn for the Nyquist column)
+    size_t glo, ghi, gstep;  // z: byte offsets of positions t + NB*m (m < E/2) and NB*(E-m) - t
+};
+
+// Line of lane (c, t) of the tile that workgroup `bid` handles: the same
+// decomposition as pass_kernel's.
+template <typename T, int MODE, int NB, int TILE, bool OFF32>
+__device__ __forceinline__ ColLine<T, OFF32> col_line(const LaunchArgs &args, int bid, int c, int t) {
+    constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
+    int sgi = 0;
+    while (sgi + 1 < args.nseg && bid >= args.seg[sgi + 1].wg_begin) ++sgi;
+    const Segment &sg = args.seg[sgi];
+    int local = bid - sg.wg_begin;
+    const int member = local % sg.group;
+    local /= sg.group;
+    const ProbArg &pa = args.p[sg.first + member];
+    // constant address space: scalar loads that do not wait for earlier stores
+    using cplan = const __attribute__((address_space(4))) DevPlan;
+    const auto &pl = *(cplan *)pa.plan;
+    const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
+    const bool nyq = local >= sg.wg_main;
+    if (nyq) local -= sg.wg_main;
+    int g = local * TILE + c;
+    ColLine<T, OFF32> cl;
+    cl.g = nullptr;
+    cl.glo = cl.ghi = cl.gstep = 0;
+    if constexpr (MODE == Z_CONV) {
+        int ky, kx;
+        if (!nyq) {
+            // rows in the order 0, 1, 2ny-1, 2, 2ny-2, ..., ny (mirror pairs in neighbouring tiles)
+            g = min(g, 2 * ny * nx - 1);
+            const int vrow = g / nx;
+            kx = g - vrow * nx;
+            ky = vrow == 0 ? 0 : (vrow == 2 * ny - 1 ? ny : ((vrow & 1) ? (vrow + 1) >> 1 : 2 * ny - (vrow >> 1)));
+            // z = t + NB*m sits in tile z/zb at row z%zb; zb divides NB
+            const int zb = pl.zb;
+            const int sh = __builtin_ctz(static_cast<unsigned>(zb));
+            const size_t off = static_cast<size_t>(ky) * zb * nx + kx +
+                               (static_cast<size_t>(t >> sh) * 2 * ny * zb + (t & (zb - 1))) * nx;
+            cl.lane = line_ptr<T, OFF32>(pa.W, off, static_cast<size_t>(NB) * 2 * ny * nx, CSZ);
+        } else {
+            g = min(g, 2 * ny - 1);
+            ky = g;
+            kx = nx;
+            cl.lane = line_ptr<T, OFF32>(pa.Wn, static_cast<size_t>(g) + static_cast<size_t>(t) * 2 * ny,
+                                         static_cast<size_t>(NB) * 2 * ny, CSZ);
+        }
+        // G~ is even in ky and kz: octant index min(k, 2n - k)
+        const int kyo = ky <= ny ? ky : 2 * ny - ky;
+        cl.g = static_cast<const char *>(nyq ? pl.Gn : pl.G);
+        const size_t gb = nyq ? static_cast<size_t>(kyo) : static_cast<size_t>(kyo) * nx + kx;
+        const size_t gs = nyq ? static_cast<size_t>(ny + 1) : static_cast<size_t>(ny + 1) * nx;
+        cl.glo = (gb + t * gs) * sizeof(T);
+        cl.ghi = (gb + (NB - t) * gs) * sizeof(T);
+        cl.gstep = static_cast<size_t>(NB) * gs * sizeof(T);
+    } else {
+        // y lines: line (z, kx) has position y at w_row(z, y) + kx; the Nyquist
+        // line of plane z is contiguous in Wn
+        if (!nyq) {
+            g = min(g, nz * nx - 1);
+            const int z = g / nx;
+            const int kx = g - z * nx;
+            const size_t es = static_cast<size_t>(pl.zb) * nx;
+            cl.lane = line_ptr<T, OFF32>(pa.W, w_row(z, 0, ny, nx, pl.zb) + kx + static_cast<size_t>(t) * es,
+                                         static_cast<size_t>(NB) * es, CSZ);
+        } else {
+            g = min(g, nz - 1);
+            cl.lane = line_ptr<T, OFF32>(pa.Wn, static_cast<size_t>(g) * 2 * ny + t, static_cast<size_t>(NB), CSZ);
+        }
+    }
+    return cl;
+}
+
+template <typename T, int E, int K, int MODE, int FIX>
+__global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) col_persist_kernel(const LaunchArgs args) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
+    static_assert(MODE == Y_FWD || MODE == Z_CONV || MODE == Y_INV, "column passes");
+    constexpr int prec = sizeof(T) == 4 ? 0 : 1;
+    constexpr int ST = FIX & 3;
+    static_assert(ST == 2 || ST == 3, "compile-time lines");
+    constexpr bool OFF32 = (FIX & 4) == 0;
+    constexpr bool ZC = MODE == Z_CONV;
+    constexpr int H = E / 2;
+    constexpr int NLOAD = MODE == Y_INV ? E : H;   // forward transforms read the stored half
+    constexpr int NSTORE = MODE == Y_FWD ? E : H;  // inverse ones keep the first half
+    constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
+    constexpr int NB = ST == 2 ? K : (E & -E) * K;
+    constexpr int TILE = pass_tile(prec, MODE, E, NB);
+    constexpr int L = E * NB;
+    constexpr int LDSW = col_stride(L, TILE, CSZ);
+    using FFT_F = LineFFT<T, E, -1, false, NB, LDSW>;
+    using FFT_I = LineFFT<T, E, +1, false, NB, LDSW>;
+
+    int bid = static_cast<int>(blockIdx.x);
+    if (bid >= args.nwg) return;
+    const int tid = threadIdx.x;
+    const int c = tid & (TILE - 1), t = tid >> __builtin_ctz(TILE);  // adjacent lanes on adjacent lines
+    // every problem of the launch has lines of length L: the same stage twiddles
+    const AxisPlan &ax0 = args.p[0].plan->ax[ZC ? 2 : 1];
+    cx<T> *twl = lds + data_elems(false, L, NB, TILE * NB, CSZ);
+    copy_to_lds<T>(twl, ax0.tw, ax0.ntw);  // published by the first transform's barrier
+
+    cx<T> ln[NLOAD];     // the loaded part of this thread's line
+    T gn[ZC ? E : 1];    // z: spectrum values of its positions
+    auto load = [&](const ColLine<T, OFF32> &cl) __attribute__((always_inline)) {
+#pragma unroll
+        for (int m = 0; m < NLOAD; ++m) ln[m] = cl.lane[m];
+        if constexpr (ZC) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const size_t idx = m < H ? m : E - m - 1;
+                const size_t o = (m < H ? cl.glo : cl.ghi) + idx * cl.gstep;
+                if constexpr (OFF32)
+                    gn[m] = *reinterpret_cast<const gbl<T> *>(as_global(cl.g) + static_cast<uint32_t>(o));
+                else
+                    gn[m] = *reinterpret_cast<const gbl<T> *>(as_global(cl.g) + o);
+            }
+        }
+    };
+    ColLine<T, OFF32> cur = col_line<T, MODE, NB, TILE, OFF32>(args, bid, c, t);
+    load(cur);
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // nothing outstanding on entry (vmcnt 0)
+    for (;;) {
+        cx<T> v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = m < NLOAD ? ln[m] : cx<T>{T(0), T(0)};
+        // the next tile's line (and spectrum values), before this tile's stores:
+        // y passes issue it before their transform, the z pass after the forward
+        // transform (the spectrum values of this tile are needed up to there)
+        const int nbid = bid + static_cast<int>(gridDim.x);
+        const bool more = nbid < args.nwg;
+        const ColLine<T, OFF32> nxt = col_line<T, MODE, NB, TILE, OFF32>(args, more ? nbid : bid, c, t);
+        if constexpr (!ZC) load(nxt);
+        // the first barrier of the first transform retires the last tile's LDS readers
+        if constexpr (MODE != Y_INV) FFT_F::template run<K>(v, ax0, lds, LDSW, twl, c, t);
+        if constexpr (ZC) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = scale(v[m], gn[m]);
+            load(nxt);
+        }
+        if constexpr (MODE != Y_FWD) FFT_I::template run<K>(v, ax0, lds, LDSW, twl, c, t);
+#pragma unroll
+        for (int m = 0; m < NSTORE; ++m) cur.lane[m] = v[m];
+        if (!more) break;
+        cur = nxt;
+        bid = nbid;
+    }
+}
+
+// Where the column kernels run persistently (PSPFFT_COL_PERSIST: 0 never,
+// 1 always, unset: where one workgroup fills a compute unit).
+inline int col_persist_mode() {
+    static int v = -2;
+    if (v == -2) {
+        v = -1;
+        if (const char *e = std::getenv("PSPFFT_COL_PERSIST")) v = std::atoi(e) != 0 ? 1 : 0;
+    }
+    return v;
+}
+
+template <typename T, int E, int K, int MODE, int FIX>
+hipError_t launch_col(const LaunchArgs &args, int grid, int block, size_t lds, hipStream_t stream) {
+    constexpr int kMaxDevices = 64;
+    static int per_cu[kMaxDevices] = {0}, cus[kMaxDevices] = {0};
+    static size_t seen_lds[kMaxDevices] = {0};
+    auto fo = pass_kernel<T, E, K, MODE, FIX>;
+    auto fp = col_persist_kernel<T, E, K, MODE, FIX>;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (per_cu[dev] == 0 || seen_lds[dev] != lds) {
+        for (auto f : {fo, fp}) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024);
+            if (e != hipSuccess) return e;
+        }
+        int p = 0, c = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, fo, block, lds);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        per_cu[dev] = p > 0 ? p : 1;
+        cus[dev] = c > 0 ? c : 1;
+        seen_lds[dev] = lds;
+    }
+    // Measured: the y passes gain where a tile's row segment is a whole
+    // 128-byte line or the values are FP32, and lose a third with FP64 tiles of
+    // 64-byte segments (lines of 2048), whose pairs of tiles share lines that
+    // long-lived workgroups no longer fetch at nearly the same time.
+    constexpr int prec = sizeof(T) == 4 ? 0 : 1;
+    constexpr int NB = (FIX & 3) == 2 ? K : (E & -E) * K;
+    constexpr bool y_ok = MODE == Z_CONV || prec == 0 ||
+                          pass_tile(prec, MODE, E, NB) * static_cast<int>(sizeof(cx<T>)) >= 128;
+    const int mode = col_persist_mode();
+    if (mode == 1 || (mode < 0 && y_ok && per_cu[dev] == 1)) {
+        int g = per_cu[dev] * cus[dev];
+        if (g > args.nwg) g = args.nwg;
+        hipLaunchKernelGGL(fp, dim3(g), dim3(block), lds, stream, args);
+    } else {
+        hipLaunchKernelGGL(fo, dim3(grid), dim3(block), lds, stream, args);
+    }
+    return hipGetLastError();
+}
+
 inline int zconv_persist_mode();
 
 // The wavefront-owned column kernel: persistent where one workgroup fills a
@@ -923,18 +1143,21 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
             if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64) && wave_col_fits<T, E, K, Y_FWD>()) {
                 if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_FWD>(args, stream);
             }
-            return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
+            if constexpr (FIX != 0) return launch_col<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
+            else return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
         case Z_CONV:
             if constexpr (FIX == 3 && wave_col_fits<T, E, K, Z_CONV>()) {
                 if (args.wave_z) return launch_wave_col<T, E, K, Z_CONV>(args, stream);
             }
             if (args.wave_z) return hipErrorInvalidValue;  // a kz-fastest spectrum needs zconv_wave_kernel
-            return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
+            if constexpr (FIX != 0) return launch_col<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
+            else return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
         case Y_INV:
             if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64) && wave_col_fits<T, E, K, Y_INV>()) {
                 if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_INV>(args, stream);
             }
-            return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
+            if constexpr (FIX != 0) return launch_col<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
+            else return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
         case X_INV: return launch_kernel<T, E, K, X_INV, FIX>(args, grid, block, lds, stream);
         default: return hipErrorInvalidValue;
     }

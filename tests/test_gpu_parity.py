@@ -224,8 +224,13 @@ def test_three_stage_lines_match_oracle(n):
 # or the LDS), so their compile-time geometry takes a smaller tile: y and z lines
 # of 1536 (24*8*8) and 2048 (16*16*8, lines of 128 threads, two wavefronts), x
 # rows of 768 (24*8*4), 1024 (16*16*4) and 2048 (16*16*8, whose split-step
-# partners go through LDS rather than the mirror lane).
-LONG_LINES = [(16, 768, 8), (16, 8, 768), (768, 8, 8), (16, 1024, 8), (16, 8, 1024), (1024, 8, 8), (2048, 8, 8)]
+# partners go through LDS rather than the mirror lane).  Their z passes fill a
+# CU with one workgroup and run persistently, as do their y passes; (80, 18,
+# 768) and (40, 18, 1024) give z workgroups several tiles each (more tiles than
+# CUs) and a partial last Nyquist tile (36 lines), whose spare lanes repeat the
+# set's last line, and (80, 768, 36) does the same for the y passes.
+LONG_LINES = [(16, 768, 8), (16, 8, 768), (768, 8, 8), (16, 1024, 8), (16, 8, 1024), (1024, 8, 8), (2048, 8, 8),
+              (80, 18, 768), (40, 18, 1024), (80, 768, 36)]
 
 
 @pytest.mark.parametrize("n", LONG_LINES)
