@@ -167,12 +167,15 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
             __syncthreads();
             const int nxt = pl + G;
             {  // y step
+                // w, the odd half's input x[y] e^{-i pi y/n}, is formed after the even
+                // transform from a copy of the column: formed up front, the two halves
+                // and the factors do not fit the 128 registers of a 1024-thread group
                 cx<T> v[E], w[E];
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int y = yt + NB * m;
                     v[m] = lds[y * SP + cp];
-                    w[m] = cmul(v[m], post[y]);
+                    w[m] = v[m];
                 }
                 // Column 0 parks its values in `sep`; the other columns go straight to W.
                 auto emit = [&](const cx<T> *q, const int parity) {
@@ -185,6 +188,8 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                 };
                 ColF::template run<K>(v, ax, lds, SP, twl, cp, yt);  // Y[2j]
                 emit(v, 0);
+#pragma unroll
+                for (int m = 0; m < E; ++m) w[m] = cmul(w[m], post[yt + NB * m]);
                 ColF::template run<K>(w, ax, lds, SP, twl, cp, yt);  // Y[2j+1]
                 emit(w, 1);
             }
