@@ -11,8 +11,10 @@
 //            Y[2j] = DFT_n(x)[j] and Y[2j+1] = DFT_n(x[y] e^{-i pi y/n})[j].
 //            Each runs with its exchange inside the column's own n LDS slots,
 //            so the plane needs no extra room.  Column 0 carries the transform
-//            C of X0 + i Xn; one wave separates the two real columns at the end
-//            with A[k] = (C[k] + conj C[-k])/2 and B[k] = (C[k] - conj C[-k])/(2i).
+//            C of X0 + i Xn; its threads, lanes of one wavefront, separate the two
+//            real columns as they store them, with A[k] = (C[k] + conj C[-k])/2
+//            and B[k] = (C[k] - conj C[-k])/(2i), the partners C[-k] coming from
+//            other lanes.
 // Inverse (W rows -> potential plane):
 //   y step : x[y] = IDFT_n(Y[2j])[y] + e^{+i pi y/n} IDFT_n(Y[2j+1])[y], y < n.
 //            Columns kx = 0 and kx = n have real results, so they are
@@ -88,12 +90,11 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
     if (pl >= args.nwg) return;
 
     // stage twiddles (n - 1 entries), exp(-i pi k / n) (k < n), and 2n slots for
-    // column 0 (forward) or the Nyquist column (inverse).  The tables depend on
-    // n only, so every problem of the launch shares them.
+    // the Nyquist column (inverse).  The tables depend on n only, so every
+    // problem of the launch shares them.
     const AxisPlan &ax = args.p[0].plan->ax[0];
     cx<T> *twl = lds + n * SP;
     const cx<T> *post = twl + (n - 1);
-    cx<T> *sep = twl + (2 * n - 1);
     copy_to_lds<T>(twl, ax.tw, 2 * n - 1);
 
     int tid = static_cast<int>(threadIdx.x);
@@ -107,6 +108,17 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
         xt = tid % NB;
         yc = tid % n;
         yt = tid / n;
+        if constexpr (FWD) {
+            // the NB threads of column 0 are lanes 0..NB-1 of wavefront 0 (threads
+            // 1..NB-1 trade places with the first threads of columns 1..NB-1)
+            if (yt == 0 && yc >= 1 && yc < NB) {
+                yt = yc;
+                yc = 0;
+            } else if (yc == 0 && yt >= 1) {
+                yc = yt;
+                yt = 0;
+            }
+        }
         cp = yc + (yc >> 4);
     };
     lanes();
@@ -177,14 +189,32 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                     v[m] = lds[y * SP + cp];
                     w[m] = v[m];
                 }
-                // Column 0 parks its values in `sep`; the other columns go straight to W.
+                // Column 0 carries C = A + i B, A and B the transforms of the real
+                // columns kx = 0 and kx = n: A[ky] = (C[ky] + conj C[-ky])/2 goes to
+                // W and B[ky] = (C[ky] - conj C[-ky])/(2i) to the Nyquist column.
+                // Its threads are lanes of wavefront 0, so the partners C[-ky] come
+                // from other lanes: position (n - j) mod n of the even half (the
+                // mirror lane, as in the split step) and n - 1 - j of the odd half.
                 auto emit = [&](const cx<T> *q, const int parity) {
-                    if (yc == 0) {
+                    if (tid < 64) {
+                        const bool col0 = yc == 0;
+                        const int lane = tid;
+                        const int addr = parity == 0 ? (lane - yt + ((NB - yt) & (NB - 1))) << 2
+                                                     : (lane - yt + (NB - 1 - yt)) << 2;
 #pragma unroll
-                        for (int m = 0; m < E; ++m) sep[2 * (yt + NB * m) + parity] = q[m];
+                        for (int m = 0; m < E; ++m) {
+                            const cx<T> d = (parity == 0 && yt == 0) ? q[(E - m) % E] : q[E - 1 - m];  // sent
+                            const cx<T> Cp = {lane_read(addr, d.x), lane_read(addr, d.y)};
+                            const cx<T> C = q[m];
+                            const cx<T> A = {static_cast<T>(0.5) * (C.x + Cp.x), static_cast<T>(0.5) * (C.y - Cp.y)};
+                            const cx<T> B = {static_cast<T>(0.5) * (C.y + Cp.y), static_cast<T>(-0.5) * (C.x - Cp.x)};
+                            at<T>(Wz, wy_off + (m * 2 * NB + parity) * rs) = col0 ? A : C;
+                            if (col0) Wnz[2 * (yt + NB * m) + parity] = B;
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < E; ++m) at<T>(Wz, wy_off + (m * 2 * NB + parity) * rs) = q[m];
                     }
-#pragma unroll
-                    for (int m = 0; m < E; ++m) at<T>(Wz, wy_off + (m * 2 * NB + parity) * rs) = q[m];
                 };
                 ColF::template run<K>(v, ax, lds, SP, twl, cp, yt);  // Y[2j]
                 emit(v, 0);
@@ -193,22 +223,12 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                 ColF::template run<K>(w, ax, lds, SP, twl, cp, yt);  // Y[2j+1]
                 emit(w, 1);
             }
-            __syncthreads();
-            // Separate column 0: C = A + i B with A, B the transforms of the real
-            // columns kx = 0 and kx = n (one entry per thread).
-            for (int ky = tid; ky < 2 * n; ky += BLK) {
-                const int kp = ky == 0 ? 0 : 2 * n - ky;
-                const cx<T> C = sep[ky];
-                const cx<T> Cp = sep[kp];
-                at<T>(Wz, ky * rs) =
-                    cx<T>{static_cast<T>(0.5) * (C.x + Cp.x), static_cast<T>(0.5) * (C.y - Cp.y)};
-                Wnz[ky] = cx<T>{static_cast<T>(0.5) * (C.y + Cp.y), static_cast<T>(-0.5) * (C.x - Cp.x)};
-            }
             if (nxt >= args.nwg) break;
             pl = nxt;
             __syncthreads();  // LDS readers of this plane are done
         }
     } else {
+        cx<T> *sep = twl + (2 * n - 1);
         constexpr int NWV = (2 * n + BLK - 1) / BLK;  // Nyquist values per thread
         cx<T> e[E];     // even W rows of this thread's column, current plane
         cx<T> nw[NWV];  // Nyquist column of the next plane, on its way to `sep`
