@@ -65,7 +65,8 @@ __device__ __forceinline__ PlaneRef plane_ref(const LaunchArgs &args, int pl) {
 }
 
 // Each workgroup takes planes blockIdx.x, blockIdx.x + gridDim.x, ...  The
-// forward kernel's stores of one plane drain while it works on the next.  The
+// forward kernel loads the next source plane before it stores the current one,
+// whose stores then drain while it works on the next.  The
 // inverse kernel loads the odd W rows of a plane while it transforms the even
 // ones, and the next plane's even rows (and Nyquist column) during the x step;
 // a whole plane of input would not fit in registers beside the one in use.
@@ -138,9 +139,10 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
 #pragma unroll
             for (int m = 0; m < H; ++m) s[m] = at<T>(plane, src_off + m * NB * CSZ);
         };
+        load_src(pl);
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // nothing outstanding on entry to the loop (vmcnt 0)
         for (;;) {
             lanes();
-            load_src(pl);
             const PlaneRef r = plane_ref(args, pl);
             const uint32_t rs = rs_of(r);                                     // W row stride (bytes)
             const uint32_t wy_off = static_cast<uint32_t>(2 * yt) * rs + yc * CSZ;  // W row 2*yt, column yc
@@ -189,6 +191,11 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                     v[m] = lds[y * SP + cp];
                     w[m] = v[m];
                 }
+                // The next source plane, before this plane's stores: loads and
+                // stores retire in order, so a load issued after them could not be
+                // waited for without waiting for them.  The last plane loads itself
+                // again, so that the loop's accesses are unconditional.
+                load_src(nxt < args.nwg ? nxt : pl);
                 // Column 0 carries C = A + i B, A and B the transforms of the real
                 // columns kx = 0 and kx = n: A[ky] = (C[ky] + conj C[-ky])/2 goes to
                 // W and B[ky] = (C[ky] - conj C[-ky])/(2i) to the Nyquist column.
