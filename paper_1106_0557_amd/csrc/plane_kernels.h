@@ -66,8 +66,8 @@ __device__ __forceinline__ PlaneRef plane_ref(const LaunchArgs &args, int pl) {
 
 // Each workgroup takes planes blockIdx.x, blockIdx.x + gridDim.x, ...  The
 // forward kernel loads the next source plane before it stores the current one,
-// whose stores then drain while it works on the next.  The
-// inverse kernel loads the odd W rows of a plane while it transforms the even
+// so the loads complete under the y transforms (the compiler's wait for them
+// still covers most of the stores issued after them).  The inverse kernel loads the odd W rows of a plane while it transforms the even
 // ones, and the next plane's even rows (and Nyquist column) during the x step;
 // a whole plane of input would not fit in registers beside the one in use.
 template <typename T, int E, int K, bool FWD>
@@ -193,9 +193,8 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                 }
                 // The next source plane, before this plane's stores: loads and
                 // stores retire in order, so a load issued after them could not be
-                // waited for without waiting for them.  The last plane loads itself
-                // again, so that the loop's accesses are unconditional.
-                load_src(nxt < args.nwg ? nxt : pl);
+                // waited for without waiting for them.
+                if (nxt < args.nwg) load_src(nxt);
                 // Column 0 carries C = A + i B, A and B the transforms of the real
                 // columns kx = 0 and kx = n: A[ky] = (C[ky] + conj C[-ky])/2 goes to
                 // W and B[ky] = (C[ky] - conj C[-ky])/(2i) to the Nyquist column.
