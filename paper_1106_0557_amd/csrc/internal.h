@@ -156,6 +156,18 @@ __host__ __device__ constexpr int max_block_for(int prec, int E) {
     return prec == 0 ? (E == 16 ? 1024 : (E <= 24 ? 512 : 256)) : (E == 16 ? 512 : 256);
 }
 
+// Line forms of the line-pass instances (template parameter FIX): FIX & 7 is
+// the number of compile-time stages (0: run-time geometry; 2, 3 or 4: radices
+// E, K / E, M, K / E, M, M, K with M the power-of-two part of E), FIX & 8 marks
+// 64-bit addresses (some array of the launch reaches 4 GB; else 32-bit lane
+// offsets).  fix_nb: threads per line.
+__host__ __device__ constexpr int fix_stages(int fix) { return fix & 7; }
+__host__ __device__ constexpr bool fix_off32(int fix) { return (fix & 7) != 0 && (fix & 8) == 0; }
+__host__ __device__ constexpr int fix_nb(int fix, int E, int K) {
+    return (fix & 7) == 2 ? K : ((fix & 7) == 3 ? (E & -E) * K : ((fix & 7) == 4 ? (E & -E) * (E & -E) * K : 0));
+}
+constexpr int kFixWide = 8;
+
 // Lines per workgroup of a line-pass launch (pass_kernel) for lines of nb
 // threads in radix family E: the default tile, halved while the workgroup
 // exceeds the family's largest or its LDS (data, stage twiddles and, for rows,

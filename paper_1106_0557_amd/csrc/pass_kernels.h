@@ -159,10 +159,27 @@ struct LineFFT {
             sync<WAVE>();
             gather(v, lds, ldsw, c, t, NB);
             stage<K, true, false, E>(v, E, 0u, twl + (E - 1), lds, ldsw, c, t, NB);
+        } else if constexpr (CNB != 0 && CNB == M * M * K) {
+            // four stages, radices E, M, M, K: Ns = 1, E, E*M, E*M*M; the twiddle
+            // tables follow one another (E - 1, E*(M - 1) and E*M*(M - 1) entries)
+            if constexpr (LEAD) sync<WAVE>();
+            stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
+            sync<WAVE>();
+            gather(v, lds, ldsw, c, t, NB);
+            sync<WAVE>();
+            stage<M, true, true, E>(v, E, 0u, twl + (E - 1), lds, ldsw, c, t, NB);
+            sync<WAVE>();
+            gather(v, lds, ldsw, c, t, NB);
+            sync<WAVE>();
+            stage<M, true, true, E * M>(v, E * M, 0u, twl + (E - 1) + E * (M - 1), lds, ldsw, c, t, NB);
+            sync<WAVE>();
+            gather(v, lds, ldsw, c, t, NB);
+            stage<K, true, false, E * M * M>(v, E * M * M, 0u, twl + (E - 1) + E * (M - 1) + E * M * (M - 1), lds,
+                                             ldsw, c, t, NB);
         } else if constexpr (CNB != 0) {
             // three stages, radices E, M, K (CNB = M*K): Ns = 1, E, E*M; the
             // twiddle tables follow one another (E - 1 and E*(M - 1) entries)
-            static_assert(CNB == M * K, "compile-time lines have two or three stages");
+            static_assert(CNB == M * K, "compile-time lines have two, three or four stages");
             if constexpr (LEAD) sync<WAVE>();
             stage<E, false, true>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
             sync<WAVE>();
@@ -260,11 +277,11 @@ __device__ __forceinline__ LinePtr<T, OFF32> line_ptr(const void *base, size_t l
     return LinePtr<T, OFF32>{const_cast<char *>(static_cast<const char *>(base)), lane_elems * esz, step_elems * esz};
 }
 
-// FIX & 3 (2 or 3): every problem of the launch has lines of that many stages
-// with radices E, (M,) K and the workgroup holds the default number of lines, so
-// the geometry is compile-time.  FIX & 4 clear: every array is below 4 GB, so
-// addresses use 32-bit lane offsets; set (FIX = 6 or 7): 64-bit addresses.
-// FIX = 0: geometry from the plan at run time, 64-bit addresses.
+// fix_stages(FIX) (2, 3 or 4): every problem of the launch has lines of that
+// many stages with radices E, (M, (M,)) K and the workgroup holds pass_tile()
+// lines, so the geometry is compile-time.  fix_off32(FIX): every array is below
+// 4 GB, so addresses use 32-bit lane offsets; otherwise (FIX & kFixWide) 64-bit
+// addresses.  FIX = 0: geometry from the plan at run time, 64-bit addresses.
 template <typename T, int E, int K, int MODE, int FIX>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pass_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -272,9 +289,9 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr bool ROW = (MODE == X_FWD || MODE == X_INV);
     constexpr int H = E / 2;  // registers m < H hold the first half of the line
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
-    constexpr int ST = FIX & 3;  // compile-time stages (0: run-time geometry)
-    constexpr bool OFF32 = ST != 0 && (FIX & 4) == 0;
-    constexpr int CNB = ST == 2 ? K : (ST == 3 ? (E & -E) * K : 0);
+    constexpr int ST = fix_stages(FIX);  // compile-time stages (0: run-time geometry)
+    constexpr bool OFF32 = fix_off32(FIX);
+    constexpr int CNB = fix_nb(FIX, E, K);
     constexpr int FTILE = pass_tile(sizeof(T) == 4 ? 0 : 1, MODE, E, CNB);
     constexpr int CL = E * CNB;  // line length when compile-time
     constexpr int CLDSW = ST ? (ROW ? row_stride(CL, CNB, CSZ) : col_stride(CL, FTILE, CSZ)) : 0;
@@ -911,15 +928,15 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) co
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
     static_assert(MODE == Y_FWD || MODE == Z_CONV || MODE == Y_INV, "column passes");
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
-    constexpr int ST = FIX & 3;
-    static_assert(ST == 2 || ST == 3, "compile-time lines");
-    constexpr bool OFF32 = (FIX & 4) == 0;
+    constexpr int ST = fix_stages(FIX);
+    static_assert(ST >= 2 && ST <= 4, "compile-time lines");
+    constexpr bool OFF32 = fix_off32(FIX);
     constexpr bool ZC = MODE == Z_CONV;
     constexpr int H = E / 2;
     constexpr int NLOAD = MODE == Y_INV ? E : H;   // forward transforms read the stored half
     constexpr int NSTORE = MODE == Y_FWD ? E : H;  // inverse ones keep the first half
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
-    constexpr int NB = ST == 2 ? K : (E & -E) * K;
+    constexpr int NB = fix_nb(FIX, E, K);
     constexpr int TILE = pass_tile(prec, MODE, E, NB);
     constexpr int L = E * NB;
     constexpr int LDSW = col_stride(L, TILE, CSZ);
@@ -1024,7 +1041,7 @@ hipError_t launch_col(const LaunchArgs &args, int grid, int block, size_t lds, h
     // 64-byte segments (lines of 2048), whose pairs of tiles share lines that
     // long-lived workgroups no longer fetch at nearly the same time.
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
-    constexpr int NB = (FIX & 3) == 2 ? K : (E & -E) * K;
+    constexpr int NB = fix_nb(FIX, E, K);
     constexpr bool y_ok = MODE == Z_CONV || prec == 0 ||
                           pass_tile(prec, MODE, E, NB) * static_cast<int>(sizeof(cx<T>)) >= 128;
     const int mode = col_persist_mode();
@@ -1163,21 +1180,27 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
     }
 }
 
-// fix: 0 (run-time geometry), 2 or 3 (compile-time lines of that many stages),
-// 6 or 7 (the same with 64-bit addresses, for arrays of 4 GB or more).
-// Three-stage instances exist where a workgroup of pass_tile() lines of M*K
-// threads fits the family's largest workgroup.
+// fix: 0 (run-time geometry), 2, 3 or 4 (compile-time lines of that many
+// stages), plus kFixWide for 64-bit addresses.  Three- and four-stage instances
+// exist where a workgroup of pass_tile() lines fits the family's largest
+// workgroup; four-stage ones where such a line (E*M*M*K points) can occur.
 template <typename T, int E, int K>
 hipError_t launch_fix(int mode, int fix, const LaunchArgs &args, int grid, int block, size_t lds,
                       hipStream_t stream) {
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
     constexpr int M = E & -E;
+    constexpr int W = kFixWide;
     if constexpr (K > 1) {
         if (fix == 2) return launch_mode<T, E, K, 2>(mode, args, grid, block, lds, stream);
-        if (fix == 6) return launch_mode<T, E, K, 6>(mode, args, grid, block, lds, stream);
+        if (fix == 2 + W) return launch_mode<T, E, K, 2 + W>(mode, args, grid, block, lds, stream);
         if constexpr (pass_tile(prec, Y_FWD, E, M * K) * M * K <= max_block_for(prec, E)) {
             if (fix == 3) return launch_mode<T, E, K, 3>(mode, args, grid, block, lds, stream);
-            if (fix == 7) return launch_mode<T, E, K, 7>(mode, args, grid, block, lds, stream);
+            if (fix == 3 + W) return launch_mode<T, E, K, 3 + W>(mode, args, grid, block, lds, stream);
+        }
+        if constexpr (M < E && E * M * M * K <= 4096 &&
+                      pass_tile(prec, Y_FWD, E, M * M * K) * M * M * K <= max_block_for(prec, E)) {
+            if (fix == 4) return launch_mode<T, E, K, 4>(mode, args, grid, block, lds, stream);
+            if (fix == 4 + W) return launch_mode<T, E, K, 4 + W>(mode, args, grid, block, lds, stream);
         }
     }
     if (fix != 0) return hipErrorInvalidValue;

@@ -139,10 +139,16 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
 #pragma unroll
             for (int m = 0; m < H; ++m) s[m] = at<T>(plane, src_off + m * NB * CSZ);
         };
-        load_src(pl);
-        __builtin_amdgcn_s_waitcnt(0x0f70);  // nothing outstanding on entry to the loop (vmcnt 0)
+        // FP32: the next plane's source is loaded during the y step (below); FP64
+        // loads it here, where the 16-byte values need no registers across the y step
+        constexpr bool PF = sizeof(T) == 4;
+        if constexpr (PF) {
+            load_src(pl);
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // nothing outstanding on entry to the loop (vmcnt 0)
+        }
         for (;;) {
             lanes();
+            if constexpr (!PF) load_src(pl);
             const PlaneRef r = plane_ref(args, pl);
             const uint32_t rs = rs_of(r);                                     // W row stride (bytes)
             const uint32_t wy_off = static_cast<uint32_t>(2 * yt) * rs + yc * CSZ;  // W row 2*yt, column yc
@@ -194,7 +200,9 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                 // The next source plane, before this plane's stores: loads and
                 // stores retire in order, so a load issued after them could not be
                 // waited for without waiting for them.
-                if (nxt < args.nwg) load_src(nxt);
+                if constexpr (PF) {
+                    if (nxt < args.nwg) load_src(nxt);
+                }
                 // Column 0 carries C = A + i B, A and B the transforms of the real
                 // columns kx = 0 and kx = n: A[ky] = (C[ky] + conj C[-ky])/2 goes to
                 // W and B[ky] = (C[ky] - conj C[-ky])/(2i) to the Nyquist column.
@@ -209,12 +217,16 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                                                      : (lane - yt + (NB - 1 - yt)) << 2;
 #pragma unroll
                         for (int m = 0; m < E; ++m) {
-                            const cx<T> d = (parity == 0 && yt == 0) ? q[(E - m) % E] : q[E - 1 - m];  // sent
-                            const cx<T> Cp = {lane_read(addr, d.x), lane_read(addr, d.y)};
+                            // every lane sends position E-1-m; thread 0's even partner is its
+                            // own register (E - m) mod E
+                            const cx<T> d = q[E - 1 - m];
+                            cx<T> Cp = {lane_read(addr, d.x), lane_read(addr, d.y)};
+                            if (parity == 0 && yt == 0) Cp = q[(E - m) % E];
                             const cx<T> C = q[m];
                             const cx<T> A = {static_cast<T>(0.5) * (C.x + Cp.x), static_cast<T>(0.5) * (C.y - Cp.y)};
                             const cx<T> B = {static_cast<T>(0.5) * (C.y + Cp.y), static_cast<T>(-0.5) * (C.x - Cp.x)};
-                            at<T>(Wz, wy_off + (m * 2 * NB + parity) * rs) = col0 ? A : C;
+                            const cx<T> o = {col0 ? A.x : C.x, col0 ? A.y : C.y};  // by value: C stays in registers
+                            at<T>(Wz, wy_off + (m * 2 * NB + parity) * rs) = o;
                             if (col0) Wnz[2 * (yt + NB * m) + parity] = B;
                         }
                     } else {

@@ -395,19 +395,21 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
             args.wave_z = gz ? 1 : 0;
             const long align = args.xcd_remap == 1 ? 8 : (args.xcd_remap == 2 ? 64 : 1);
             const int grid = static_cast<int>((wg + align - 1) / align * align);
-            // compile-time geometry when every line has two stages (radices E, K)
-            // or three (E, M, K) and the workgroup holds the default number of
-            // lines; 32-bit offsets when every array is below 4 GB (else fix + 4)
+            // compile-time geometry when every line has two stages (radices E, K),
+            // three (E, M, K) or four (E, M, M, K) and the workgroup holds
+            // pass_tile() lines; 32-bit offsets when every array is below 4 GB
+            // (else fix + kFixWide)
             const int M = E & -E;
             int fix = 0;
             if (K > 1) {
                 const AxisPlan &a0 = plans[idx[c0]]->host.ax[axis];
                 if (a0.nst == 2) fix = 2;
                 else if (a0.nst == 3 && a0.R[1] == M) fix = 3;
-                const int cnb = fix == 2 ? K : M * K;
+                else if (a0.nst == 4 && a0.R[1] == M && a0.R[2] == M && M < E && E * M * M * K <= 4096) fix = 4;
+                const int cnb = pspfft::fix_nb(fix, E, K);
                 if (fix && !gz && block != pspfft::pass_tile(prec, mode, E, cnb) * cnb) fix = 0;
                 if (fix && gz && block != pspfft::fix_tile(prec, mode, cnb) * cnb) fix = 0;
-                if (fix == 3 && pspfft::pass_tile(prec, pspfft::Y_FWD, E, cnb) * cnb > pspfft::max_block_for(prec, E))
+                if (fix >= 3 && pspfft::pass_tile(prec, pspfft::Y_FWD, E, cnb) * cnb > pspfft::max_block_for(prec, E))
                     fix = 0;
                 bool wide = false;
                 for (size_t j = c0; j < c1 && fix; ++j) {
@@ -415,7 +417,7 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
                     if (ax.nst != a0.nst || ax.NB != cnb) fix = 0;
                     if (!arrays_below_4gb(plans[idx[j]])) wide = true;
                 }
-                if (fix && wide) fix += 4;
+                if (fix && wide) fix += pspfft::kFixWide;
             }
             if (gz && fix != 3) return PSPFFT_ERR_UNSUPPORTED_SIZE;  // only zconv_wave_kernel reads that layout
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "

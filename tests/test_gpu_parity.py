@@ -247,6 +247,31 @@ def test_long_lines_match_oracle(n):
     assert r32["rel_l2"] <= FP32_TOL
 
 
+# Lines of four stages (radices E, M, M, K) with compile-time geometry: z lines
+# of 1152 (36*4*4*2), 2304 (36*4*4*4), 640 (20*4*4*2) and 3072 (24*8*8*2, FP32
+# only: FP64 meshes stop at 1152), y lines of 1152 and 1280 (20*4*4*4), x rows of
+# 1152 and 640.
+FOUR_STAGE = [(16, 8, 576), (16, 8, 1152), (16, 8, 320), (16, 8, 1536), (16, 576, 8), (16, 640, 8), (1152, 8, 8),
+              (640, 8, 8)]
+
+
+@pytest.mark.parametrize("n", FOUR_STAGE)
+def test_four_stage_lines_match_oracle(n):
+    say(f"[four-stage] n={n}")
+    h = (0.02, 0.03, 0.025)
+    S = sources.random_field(n, seed=sum(n) + 7).numpy()
+    ref = oracle.solve_fft(S, h)
+    if max(n) <= 1152:
+        got64 = gpu_solve(n, h, S, torch.float64)
+        r64 = norms.report(got64, ref)
+        say(f"  fp64 {r64}")
+        assert r64["rel_l2"] <= FP64_TOL and r64["rel_max"] <= FP64_TOL
+    got32 = gpu_solve(n, h, S, torch.float32)
+    r32 = norms.report(got32, ref)
+    say(f"  fp32 {r32}")
+    assert r32["rel_l2"] <= FP32_TOL
+
+
 def test_zero_source_gives_zero_potential():
     say("[zero source]")
     n = (24, 16, 20)
