@@ -29,8 +29,9 @@
 namespace pspfft {
 
 // CNB, CLDSW: threads per line and LDS stride when known at compile time (a
-// two-stage line, L = E*K and CNB = K, or a three-stage line with radices E, M,
-// K, L = E*M*K and CNB = M*K, in a workgroup of the default tile), else 0.
+// two-stage line, L = E*K and CNB = K; three stages with radices E, M, K,
+// L = E*M*K and CNB = M*K; or four, E, M, M, K, L = E*M*M*K and CNB = M*M*K),
+// else 0.
 template <typename T, int E, int DIR, bool ROW, int CNB = 0, int CLDSW = 0>
 struct LineFFT {
     static constexpr int M = E & -E;  // radix of the middle stages
