@@ -1167,7 +1167,7 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
             if constexpr (FIX == 3 && wave_col_fits<T, E, K, Z_CONV>()) {
                 if (args.wave_z) return launch_wave_col<T, E, K, Z_CONV>(args, stream);
             }
-            if (args.wave_z) return hipErrorInvalidValue;  // a kz-fastest spectrum needs zconv_wave_kernel
+            if (args.wave_z) return hipErrorInvalidValue;  // a kz-fastest spectrum needs wave_col_kernel
             if constexpr (FIX != 0) return launch_col<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
             else return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
         case Y_INV:

@@ -279,7 +279,7 @@ bool arrays_below_4gb(pspfft_plan_t p) {
     return ws_bytes(p->n, p->prec) < lim && nx * ny * nz * r < lim && (nz + 1) * (ny + 1) * nx * r < lim;
 }
 
-// The z pass runs by wavefront-owned lines (zconv_wave_kernel) where its lines
+// The z pass runs by wavefront-owned lines (wave_col_kernel) where its lines
 // have three stages E, M, K with M*K = 32 or 64 threads, or 16 threads where the
 // tile's rows take more than half the LDS (one workgroup per CU; measured, the
 // smaller 16-thread tiles gain nothing over the column kernel), the
@@ -419,7 +419,7 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_p
                 }
                 if (fix && wide) fix += pspfft::kFixWide;
             }
-            if (gz && fix != 3) return PSPFFT_ERR_UNSUPPORTED_SIZE;  // only zconv_wave_kernel reads that layout
+            if (gz && fix != 3) return PSPFFT_ERR_UNSUPPORTED_SIZE;  // only wave_col_kernel reads that layout
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "
                           "threads, %zu B LDS", mode, prec, E, K, fix, args.count, args.nseg, wg, block, lds);
             if (pspfft::launch_pass(mode, prec, E, K, fix, args, grid, block, lds, stream) != hipSuccess)
