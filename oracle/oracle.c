@@ -303,6 +303,7 @@ int oracle_direct(int nx, int ny, int nz, const double h[3], const double *S, lo
     long nxy = (long)nx * ny, n = nxy * nz;
     double *tab = (double *)malloc(sizeof(double) * (size_t)n);
     if (!tab) return -1;
+#pragma omp parallel for schedule(static)
     for (long r = 0; r < nz; ++r)
         for (long q = 0; q < ny; ++q)
             for (long p = 0; p < nx; ++p) tab[(r * ny + q) * nx + p] = oracle_green_value(p, q, r, h);

@@ -146,6 +146,54 @@ def test_paper_problem_converges_on_gpu(kind):
     assert order > 1.0
 
 
+@pytest.mark.parametrize("kind", ["sphere", "spheroid", "binary"])
+def test_paper_resolutions_48_144_288(kind):
+    """The first three of the paper's resolutions (Sec. 4.1-4.3 convergence figures),
+    FP32: the L1 error falls at every step and faster than first order overall."""
+    errs = []
+    for n in (48, 144, 288):
+        mesh, h, origin, S, f = problem(kind, n)
+        phi = gpu_solve(mesh, h, S, torch.float32)
+        del S
+        errs.append(l1_on_device(phi, mesh, h, origin, f))
+        say(f"[paper resolutions] {kind} n={n} mesh={mesh}: L1 {errs[-1]:.4e}")
+        del phi
+        torch.cuda.empty_cache()
+    order = math.log(errs[0] / errs[-1]) / math.log(288 / 48)
+    say(f"  order 48 -> 288: {order:.2f}")
+    assert errs[0] > errs[1] > errs[2]
+    assert order > 1.0
+
+
+@pytest.mark.parametrize("n", [576, 1152])
+def test_largest_paper_meshes_sampled_direct_sum(n):
+    """576^3 and 1152^3 (1152^3 and 2304^3 padded: lines of four stages in the
+    9 * 2^a family), FP32, the sphere problem of Sec. 4.1, at 64 sampled cells
+    against the oracle's direct sum."""
+    from paper_1106_0557_amd import Plan
+
+    mesh, h, origin, S, f = problem("sphere", n, sub=1)
+    S32 = S.to(torch.float32)
+    size = n**3
+    rng = np.random.default_rng(n)
+    targets = np.unique(np.concatenate([rng.integers(0, size, size=60), [0, size - 1, size // 2 + n // 2,
+                                                                          (n // 2) * (n * n + n + 1)]]))
+    say(f"[largest] n={n}: {targets.size} targets")
+    plan = Plan(*mesh, h=h, dtype=torch.float32)
+    phi = plan.solve(S32)
+    torch.cuda.synchronize()
+    got = phi.reshape(-1)[torch.from_numpy(targets).cuda()].double().cpu().numpy()
+    plan.close()
+    del phi, S32
+    torch.cuda.empty_cache()
+    S_host = S.cpu().numpy()
+    del S
+    want = oracle.direct(S_host, h, targets)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say(f"  sampled rel max err {err:.3e}")
+    assert err <= 1e-5
+
+
 @pytest.mark.skipif(os.environ.get("PSPFFT_SWEEP") != "1", reason="full sweep only with PSPFFT_SWEEP=1")
 def test_convergence_sweep_at_paper_resolutions():
     out = {}

@@ -79,7 +79,8 @@ def test_fft3d_matches_numpy(oracle_lib):
 
 @pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (0.3, 0.2, 0.5), (0.1, 0.4, 0.05), (2.0, 2.0, 3.0)])
 def test_self_cell_is_largest_off_origin_value(oracle_lib, h):
-    """Sec. 2.1: G(0,0,0) is set equal to the largest off-origin value on the mesh."""
+    """Sec. 2.1, Eq. (greens_function): the self cell takes -hx hy hz / (4 pi min h), the
+    off-origin value of greatest magnitude (one step along the finest axis)."""
     g0 = oracle_lib.green_value(0, 0, 0, h)
     axis = int(np.argmin(h))
     step = [0, 0, 0]
@@ -359,3 +360,67 @@ def test_anisotropic_rectangular_grid_follows_the_axes(oracle_lib):
     # the wrong axis assignment of h is clearly detected
     wrong = oracle_lib.solve_fft(S, h[::-1])
     assert norms.l1(wrong, ref) > 10 * norms.l1(phi, ref)
+
+
+def test_binary_spheroid_closed_form_is_a_potential():
+    """Sec. 4.3: two homogeneous oblate spheroids centred on the x axis.  Checked by
+    what any potential of that mass distribution must satisfy, with asymmetric
+    centres so that a sign error in the shift or a dropped body shows."""
+    from oracle import closed_forms as cf
+
+    a, e, Grho = 0.5, 0.28, 1.0
+    b = a * math.sqrt(1 - e * e)
+    cs = (-0.7, 1.1)
+    f = lambda x, y, z: cf.phi_binary_spheroid(x, y, z, a, b, cs, Grho)  # noqa: E731
+    # Poisson: 4 pi G rho inside either body, 0 between and around them
+    for c in cs:
+        assert _lap(f, c + 0.1, 0.05, -0.03) == pytest.approx(4 * math.pi * Grho, rel=1e-5)
+        assert abs(_lap(f, c, 0.0, b + 0.05)) <= 1e-4
+    assert abs(_lap(f, 0.2, 0.0, 0.0)) <= 1e-4
+    assert abs(_lap(f, 2.0, 0.3, 0.1)) <= 1e-4
+    # the short axis is z: just inside along y, just outside along z
+    assert _lap(f, cs[0], a - 0.005, 0.0) == pytest.approx(4 * math.pi * Grho, rel=1e-5)
+    assert abs(_lap(f, cs[0], 0.0, b + 0.005)) <= 1e-4
+    # continuous across each surface
+    for c in cs:
+        for th in (0.2, 0.9, 1.4):
+            p = np.array([a * math.sin(th), 0.0, b * math.cos(th)])
+            lo, hi = p * (1 - 1e-10), p * (1 + 1e-10)
+            assert f(c + lo[0], lo[1], lo[2]) == pytest.approx(f(c + hi[0], hi[1], hi[2]), rel=1e-8)
+    # far field: the total mass 2 M = 2 (4/3 pi a^2 b rho) seen from far away
+    M2 = 2 * 4 / 3 * math.pi * a * a * b
+    r = np.array([4e3, -1e3, 2e3])
+    assert f(*r) == pytest.approx(-Grho * M2 / np.linalg.norm(r), rel=1e-4)
+    # symmetric centres give a potential even in x
+    g = lambda x: cf.phi_binary_spheroid(x, 0.3, 0.2, a, b, (-1.0, 1.0), Grho)  # noqa: E731
+    for x in (0.1, 0.8, 1.3, 2.5):
+        assert g(x) == pytest.approx(g(-x), rel=1e-13)
+    # deeper inside a body than anywhere between the two
+    assert f(cs[1], 0, 0) < f(0.2, 0, 0)
+
+
+# ------------------------------------------------------------------ norms --
+
+def test_error_norms_on_hand_computed_cases():
+    """The error measures on cases worked by hand.  phi = [1, 3], ref = [1, 1]:
+    |d| = [0, 2], so L1 = 2/2, rel L2 = 2/sqrt(2), rel max = 2/1."""
+    from oracle import norms
+
+    assert norms.l1([1.0, 3.0], [1.0, 1.0]) == pytest.approx(1.0, rel=1e-15)
+    assert norms.rel_l2([1.0, 3.0], [1.0, 1.0]) == pytest.approx(math.sqrt(2.0), rel=1e-15)
+    assert norms.rel_max([1.0, 3.0], [1.0, 1.0]) == pytest.approx(2.0, rel=1e-15)
+    # signed differences that cancel, and a reference whose largest magnitude is
+    # negative: phi = [0, -1], ref = [-2, 1], d = [2, -2]
+    phi, ref = [0.0, -1.0], [-2.0, 1.0]
+    assert norms.l1(phi, ref) == pytest.approx(4.0 / 3.0, rel=1e-15)
+    assert norms.rel_l2(phi, ref) == pytest.approx(math.sqrt(8.0 / 5.0), rel=1e-15)
+    assert norms.rel_max(phi, ref) == pytest.approx(1.0, rel=1e-15)
+    # the denominators are the reference's, not the result's
+    phi, ref = [-3.0, 1.0, 10.0], [-4.0, 1.0, 9.0]
+    assert norms.l1(phi, ref) == pytest.approx(2.0 / 14.0, rel=1e-15)
+    assert norms.rel_l2(phi, ref) == pytest.approx(math.sqrt(2.0 / 98.0), rel=1e-15)
+    assert norms.rel_max(phi, ref) == pytest.approx(1.0 / 9.0, rel=1e-15)
+    # shape does not matter, identical arrays give zero
+    x = RNG.standard_normal((3, 4, 5))
+    assert norms.report(x, x) == {"l1": 0.0, "rel_l2": 0.0, "rel_max": 0.0}
+    assert norms.rel_l2(x * 1.5, x) == pytest.approx(0.5, rel=1e-14)
