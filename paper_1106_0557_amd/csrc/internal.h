@@ -38,11 +38,14 @@ constexpr int kMaxProblems = 32;  // problems per grouped launch
 // t + NB*m (m < E) before the first and after the last stage; the upper half of
 // the input (m >= E/2) is the zero padding and the upper half of the output is
 // never needed, so both are known at compile time.
+//
+// Lengths outside the families (E = 0, NB = 0) run on the generic line kernel
+// (line_generic.hip) with stages of radix 8, 4 or 2, then 5, 9 and 3.
 struct AxisPlan {
     int n;        // mesh cells along the axis
     int L;        // transform length (2n for y and z, n for x)
-    int E;        // elements per thread (radix family: 16, 20, 24 or 36)
-    int NB;       // threads per line
+    int E;        // elements per thread (radix family: 16, 20, 24 or 36; 0: generic kernel)
+    int NB;       // threads per line (0: generic kernel)
     int nst;      // number of stages
     int ntw;      // entries in the twiddle table
     int R[kMaxStages];          // radix of stage s
@@ -87,6 +90,7 @@ struct LaunchArgs {
     int nwg;          // workgroups doing work (the grid may be padded to a multiple of 8)
     int xcd_remap;    // renumber workgroups so each XCD gets a contiguous range
     int wave_z;       // z pass: spectra kz-fastest, lines kept within one wavefront
+    int gtile;        // generic line kernel: lines per workgroup
     Segment seg[kMaxProblems];
     ProbArg p[kMaxProblems];
 };
@@ -259,6 +263,11 @@ inline hipError_t launch_plane(bool fwd, int prec, int E, int K, const LaunchArg
         default: return hipErrorInvalidValue;
     }
 }
+
+// Generic line kernel (any 2^a 3^b 5^c length): `grid` workgroups of 256
+// threads, each owning args.gtile lines, with `lds` bytes of LDS (two buffers of
+// gtile * (L + 1) complex values for the longest line of the launch).
+hipError_t launch_generic(int mode, int prec, const LaunchArgs &args, int grid, size_t lds, hipStream_t stream);
 
 // Green's-function spectrum in FP64: fills the octant (nz+1)(ny+1)(nx+1) of G
 // into `a`, applies the even-extension cosine transform along each axis (using

@@ -1,0 +1,287 @@
+// line_generic.hip -- the five passes for transform lengths outside the radix
+// families of pass_kernels.h: any L = 2^a 3^b 5^c (odd parts beyond 1, 3, 5, 9,
+// lines shorter than a family's element count, FP64 lines beyond the family
+// limits).  Same passes, same workspace and spectrum layouts and the same
+// unnormalised transforms as the family kernels (Sec. 2.1 mesh doubling, Sec.
+// 2.2.2 sequence of 1D transforms), so one plan may mix family and generic axes.
+//
+// A workgroup of 256 threads owns `tile` whole lines.  The lines are loaded into
+// one of two LDS buffers; every stage (radix R in {2, 3, 4, 5, 8, 9}, Stockham
+// autosort, decimation in time) reads one buffer and writes the other:
+//   for each butterfly j < L/R of a line, k = j mod Ns:
+//     x_r = in[j + r L/R] * exp(DIR 2 pi i r k / (Ns R)),  r < R
+//     out[(j - k) R + k + r Ns] = DFT_R(x)[r]
+// with Ns the product of the earlier radices; the result is in natural order.
+// Column passes (y, z) keep element (line c, position p) at p*tile + c, so a
+// wavefront's global accesses cover `tile` adjacent kx and its LDS accesses are
+// consecutive; row passes (x) keep it at c*(L+1) + p.
+#include "fft_core.h"
+#include "internal.h"
+
+namespace pspfft {
+namespace {
+
+constexpr int kGenBlock = 256;
+
+template <bool ROW>
+__device__ __forceinline__ int gidx(int c, int p, int tile, int L) {
+    return ROW ? c * (L + 1) + p : p * tile + c;
+}
+
+// One stage of radix R over every line of the tile: src -> dst.
+template <typename T, int R, int DIR, bool ROW>
+__device__ void gen_stage(const cx<T> *src, cx<T> *dst, int tile, int L, int Ns, const cx<T> *tw) {
+    const int nb = L / R;  // butterflies per line
+    const int total = tile * nb;
+    for (int w = threadIdx.x; w < total; w += kGenBlock) {
+        int c, j;
+        if constexpr (ROW) {
+            c = w / nb;
+            j = w - c * nb;
+        } else {
+            j = w / tile;
+            c = w - j * tile;
+        }
+        const int k = j % Ns;
+        cx<T> x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = src[gidx<ROW>(c, j + r * nb, tile, L)];
+        if (Ns > 1) {
+            const cx<T> *t = tw + static_cast<size_t>(k) * (R - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = DIR > 0 ? cmulc(x[r], t[r - 1]) : cmul(x[r], t[r - 1]);
+        }
+        dft<R, DIR>(x);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[gidx<ROW>(c, base + r * Ns, tile, L)] = x[r];
+    }
+}
+
+// Transform every line of the tile held in `a` (the other buffer `b` is
+// scratch).  Returns the buffer that holds the result.  Opens with a barrier, so
+// the caller's writes to `a` are visible, and ends with one.
+template <typename T, int DIR, bool ROW>
+__device__ cx<T> *gen_transform(cx<T> *a, cx<T> *b, int tile, const AxisPlan &ax) {
+    const cx<T> *tw = static_cast<const cx<T> *>(ax.tw);
+    for (int s = 0; s < ax.nst; ++s) {
+        __syncthreads();
+        const cx<T> *t = tw + ax.twoff[s];
+        switch (ax.R[s]) {
+            case 2: gen_stage<T, 2, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
+            case 3: gen_stage<T, 3, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
+            case 4: gen_stage<T, 4, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
+            case 5: gen_stage<T, 5, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
+            case 8: gen_stage<T, 8, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
+            case 9: gen_stage<T, 9, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
+            default: break;  // the host builds only these radices
+        }
+        cx<T> *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    __syncthreads();
+    return a;
+}
+
+// Element p of column line g of a y pass (lines (z, kx), Nyquist lines z) or a
+// z pass (lines (ky, kx), Nyquist lines ky).
+template <typename T, int MODE>
+__device__ __forceinline__ cx<T> *col_elem(const DevPlan &pl, cx<T> *W, cx<T> *Wn, bool nyq, long g, int p) {
+    const int nx = pl.nx, ny = pl.ny;
+    if constexpr (MODE == Z_CONV) {
+        if (nyq) return Wn + static_cast<size_t>(p) * 2 * ny + g;
+        const int ky = static_cast<int>(g / nx), kx = static_cast<int>(g - static_cast<long>(ky) * nx);
+        return W + w_row(p, ky, ny, nx, pl.zb) + kx;
+    } else {
+        if (nyq) return Wn + static_cast<size_t>(g) * 2 * ny + p;
+        const int z = static_cast<int>(g / nx), kx = static_cast<int>(g - static_cast<long>(z) * nx);
+        return W + w_row(z, p, ny, nx, pl.zb) + kx;
+    }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kGenBlock) generic_kernel(const LaunchArgs args) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr bool ROW = (MODE == X_FWD || MODE == X_INV);
+    constexpr int axis = ROW ? 0 : (MODE == Z_CONV ? 2 : 1);
+    const int bid = static_cast<int>(blockIdx.x);
+    if (bid >= args.nwg) return;
+    int sgi = 0;
+    while (sgi + 1 < args.nseg && bid >= args.seg[sgi + 1].wg_begin) ++sgi;
+    const Segment &sg = args.seg[sgi];
+    int local = bid - sg.wg_begin;
+    const int member = local % sg.group;  // tile-major, as in the family kernels
+    local /= sg.group;
+    const ProbArg &pa = args.p[sg.first + member];
+    const DevPlan &pl = *pa.plan;
+    const AxisPlan &ax = pl.ax[axis];
+    const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
+    const int L = ax.L;
+    const int tile = args.gtile;
+    cx<T> *A = reinterpret_cast<cx<T> *>(smem);
+    cx<T> *B = A + static_cast<size_t>(tile) * (L + 1);
+    cx<T> *W = static_cast<cx<T> *>(pa.W);
+    cx<T> *Wn = static_cast<cx<T> *>(pa.Wn);
+    const bool nyq = local >= sg.wg_main;
+    if (nyq) local -= sg.wg_main;
+    const long g0 = static_cast<long>(local) * tile;
+    const int tid = threadIdx.x;
+    const cx<T> zero = {T(0), T(0)};
+
+    if constexpr (MODE == X_FWD) {
+        // rows r = z*ny + y of S, zero-padded to 2nx, packed u[j] = s[2j] + i s[2j+1] (L = nx)
+        const long nrows = static_cast<long>(ny) * nz;
+        const T *S = static_cast<const T *>(pa.S);
+        for (int w = tid; w < tile * L; w += kGenBlock) {
+            const int c = w / L, j = w - c * L;
+            const long g = g0 + c;
+            cx<T> v = zero;
+            if (g < nrows) {
+                const T *row = S + static_cast<size_t>(g) * nx;
+                if (2 * j < nx) v.x = row[2 * j];
+                if (2 * j + 1 < nx) v.y = row[2 * j + 1];
+            }
+            A[gidx<true>(c, j, tile, L)] = v;
+        }
+        const cx<T> *U = gen_transform<T, -1, true>(A, B, tile, ax);
+        // split step: X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k]), k <= n
+        const cx<T> *post = static_cast<const cx<T> *>(ax.post);
+        for (int w = tid; w < tile * (L + 1); w += kGenBlock) {
+            const int c = w / (L + 1), k = w - c * (L + 1);
+            const long g = g0 + c;
+            if (g >= nrows) continue;
+            const cx<T> u = U[gidx<true>(c, k == L ? 0 : k, tile, L)];
+            const cx<T> m = U[gidx<true>(c, k == 0 ? 0 : L - k, tile, L)];
+            const cx<T> a = {static_cast<T>(0.5) * (u.x + m.x), static_cast<T>(0.5) * (u.y - m.y)};
+            const cx<T> b = {static_cast<T>(0.5) * (u.x - m.x), static_cast<T>(0.5) * (u.y + m.y)};
+            const cx<T> e = k < L ? post[k] : cx<T>{T(-1), T(0)};
+            const cx<T> eb = cmul(e, b);
+            const cx<T> X = {a.x + eb.y, a.y - eb.x};  // a - i e b
+            const int z = static_cast<int>(g / ny), y = static_cast<int>(g - static_cast<long>(z) * ny);
+            if (k < nx) W[w_row(z, y, ny, nx, pl.zb) + k] = X;
+            else Wn[static_cast<size_t>(z) * 2 * ny + y] = X;
+        }
+    } else if constexpr (MODE == X_INV) {
+        // X[k], k <= n, of rows y < ny; Hermitian extension through the inverse split step
+        const long nrows = static_cast<long>(ny) * nz;
+        for (int w = tid; w < tile * (L + 1); w += kGenBlock) {
+            const int c = w / (L + 1), k = w - c * (L + 1);
+            const long g = g0 + c;
+            cx<T> v = zero;
+            if (g < nrows) {
+                const int z = static_cast<int>(g / ny), y = static_cast<int>(g - static_cast<long>(z) * ny);
+                v = k < nx ? W[w_row(z, y, ny, nx, pl.zb) + k] : Wn[static_cast<size_t>(z) * 2 * ny + y];
+            }
+            B[gidx<true>(c, k, tile, L)] = v;  // L + 1 slots per row
+        }
+        __syncthreads();
+        // U[k] = (X[k] + X*[n-k]) + i exp(+i pi k/n) (X[k] - X*[n-k]), k < n
+        const cx<T> *post = static_cast<const cx<T> *>(ax.post);
+        for (int w = tid; w < tile * L; w += kGenBlock) {
+            const int c = w / L, k = w - c * L;
+            const cx<T> xk = B[gidx<true>(c, k, tile, L)];
+            const cx<T> xm = B[gidx<true>(c, L - k, tile, L)];
+            const cx<T> e = {xk.x + xm.x, xk.y - xm.y};
+            const cx<T> o = cmulc(cx<T>{xk.x - xm.x, xk.y + xm.y}, post[k]);  // times exp(+i pi k/n)
+            A[gidx<true>(c, k, tile, L)] = cx<T>{e.x - o.y, e.y + o.x};     // e + i o
+        }
+        const cx<T> *u = gen_transform<T, +1, true>(A, B, tile, ax);
+        T *Phi = static_cast<T *>(pa.Phi);
+        for (int w = tid; w < tile * nx; w += kGenBlock) {
+            const int c = w / nx, x = w - c * nx;
+            const long g = g0 + c;
+            if (g >= nrows) continue;
+            const cx<T> v = u[gidx<true>(c, x >> 1, tile, L)];
+            Phi[static_cast<size_t>(g) * nx + x] = (x & 1) ? v.y : v.x;
+        }
+    } else {
+        // column lines: y passes over (z, kx), z pass over (ky, kx); Nyquist lines kx = nx
+        long nlines;
+        int nin, nout;  // positions read (the rest is zero padding) and written
+        if constexpr (MODE == Z_CONV) {
+            nlines = nyq ? 2L * ny : 2L * ny * nx;
+            nin = nz;
+            nout = nz;
+        } else {
+            nlines = nyq ? static_cast<long>(nz) : static_cast<long>(nz) * nx;
+            nin = MODE == Y_FWD ? ny : L;
+            nout = MODE == Y_FWD ? L : ny;
+        }
+        for (int w = tid; w < tile * L; w += kGenBlock) {
+            const int p = w / tile, c = w - p * tile;
+            const long g = g0 + c;
+            cx<T> v = zero;
+            if (g < nlines && p < nin) v = *col_elem<T, MODE>(pl, W, Wn, nyq, g, p);
+            A[gidx<false>(c, p, tile, L)] = v;
+        }
+        cx<T> *res;
+        if constexpr (MODE == Z_CONV) {
+            res = gen_transform<T, -1, false>(A, B, tile, ax);
+            // multiply by the spectrum, even in ky and kz: octant index min(k, 2n - k)
+            const T *G = static_cast<const T *>(pl.G);
+            const T *Gn = static_cast<const T *>(pl.Gn);
+            for (int w = tid; w < tile * L; w += kGenBlock) {
+                const int kz = w / tile, c = w - kz * tile;
+                const long g = g0 + c;
+                if (g >= nlines) continue;
+                const int kzo = kz <= nz ? kz : L - kz;
+                T gv;
+                if (nyq) {
+                    const int ky = static_cast<int>(g), kyo = ky <= ny ? ky : 2 * ny - ky;
+                    gv = Gn[static_cast<size_t>(kzo) * (ny + 1) + kyo];
+                } else {
+                    const int ky = static_cast<int>(g / nx), kx = static_cast<int>(g - static_cast<long>(ky) * nx);
+                    const int kyo = ky <= ny ? ky : 2 * ny - ky;
+                    gv = G[(static_cast<size_t>(kzo) * (ny + 1) + kyo) * nx + kx];
+                }
+                cx<T> &e = res[gidx<false>(c, kz, tile, L)];
+                e = cx<T>{e.x * gv, e.y * gv};
+            }
+            res = gen_transform<T, +1, false>(res, res == A ? B : A, tile, ax);
+        } else {
+            res = gen_transform<T, MODE == Y_FWD ? -1 : +1, false>(A, B, tile, ax);
+        }
+        for (int w = tid; w < tile * nout; w += kGenBlock) {
+            const int p = w / tile, c = w - p * tile;
+            const long g = g0 + c;
+            if (g < nlines) *col_elem<T, MODE>(pl, W, Wn, nyq, g, p) = res[gidx<false>(c, p, tile, L)];
+        }
+    }
+}
+
+template <typename T, int MODE>
+hipError_t launch_gen(const LaunchArgs &args, int grid, size_t lds, hipStream_t stream) {
+    static bool attr_set = false;
+    auto fn = generic_kernel<T, MODE>;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kGenBlock), lds, stream, args);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gen_mode(int mode, const LaunchArgs &args, int grid, size_t lds, hipStream_t stream) {
+    switch (mode) {
+        case X_FWD: return launch_gen<T, X_FWD>(args, grid, lds, stream);
+        case Y_FWD: return launch_gen<T, Y_FWD>(args, grid, lds, stream);
+        case Z_CONV: return launch_gen<T, Z_CONV>(args, grid, lds, stream);
+        case Y_INV: return launch_gen<T, Y_INV>(args, grid, lds, stream);
+        case X_INV: return launch_gen<T, X_INV>(args, grid, lds, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_generic(int mode, int prec, const LaunchArgs &args, int grid, size_t lds, hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
+    return prec == 0 ? launch_gen_mode<float>(mode, args, grid, lds, stream)
+                     : launch_gen_mode<double>(mode, args, grid, lds, stream);
+}
+
+}  // namespace pspfft

@@ -132,12 +132,30 @@ int family_of_len(int L) {
 
 int axis_len(int axis, int n) { return axis == 0 ? n : 2 * n; }
 
+// Largest mesh size of the radix-family kernels per precision (y and z; the
+// packed x transform has length n, so x may be twice as long).
 int max_n(pspfft_precision p) { return p == PSPFFT_FP32 ? 2048 : 1152; }
 
-// The packed x transform has length n, so x may be twice as long as y and z.
-bool size_ok(int axis, int n, pspfft_precision p) {
+// Largest mesh size of the generic line kernel, any axis and precision: the
+// doubled line of 2n <= 4096 points and its two LDS buffers fit one workgroup.
+constexpr int kGenericMaxN = 2048;
+
+// n = 2^a 3^b 5^c
+bool smooth235(int n) {
+    if (n < 1) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// The axis runs on a radix family's kernels (else on the generic line kernel).
+bool family_axis(int axis, int n, pspfft_precision p) {
     const int lim = axis == 0 ? 2 * max_n(p) : max_n(p);
     return n >= 1 && n <= lim && family_of_len(axis_len(axis, n)) != 0;
+}
+
+bool size_ok(int axis, int n, pspfft_precision p) {
+    return family_axis(axis, n, p) || (n >= 1 && n <= kGenericMaxN && smooth235(n));
 }
 
 bool sizes_ok(int nx, int ny, int nz, pspfft_precision p) {
@@ -161,26 +179,47 @@ void turn(long j, long M, double &c, double &s) {
     if (neg_s) s = -s;
 }
 
-// Stage plan and FP64 twiddles of one axis.
-bool build_axis(int axis, int n, AxisPlan &ax, std::vector<std::complex<double>> &tw) {
+// Radices of the generic line kernel for a length L = 2^a 3^b 5^c, in stage
+// order: 8s, then one 4 or 2, then 5s, 9s and a last 3.
+std::vector<int> generic_radices(int L) {
+    std::vector<int> r;
+    int m = L, p2 = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++p2;
+    }
+    for (; p2 >= 3; p2 -= 3) r.push_back(8);
+    if (p2 == 2) r.push_back(4);
+    if (p2 == 1) r.push_back(2);
+    for (; m % 5 == 0; m /= 5) r.push_back(5);
+    for (; m % 9 == 0; m /= 9) r.push_back(9);
+    for (; m % 3 == 0; m /= 3) r.push_back(3);
+    return r;
+}
+
+// Stage plan and FP64 twiddles of one axis: a radix family's stages (every
+// radix divides E) where the family kernels take the length, else the generic
+// kernel's radices.
+bool build_axis(int axis, int n, pspfft_precision prec, AxisPlan &ax, std::vector<std::complex<double>> &tw) {
     const int L = axis_len(axis, n);
-    const int E = family_of_len(L);
-    if (!E) return false;
+    const int E = family_axis(axis, n, prec) ? family_of_len(L) : 0;
+    if (!E && !(n <= kGenericMaxN && smooth235(n))) return false;
     std::memset(&ax, 0, sizeof(ax));
     ax.n = n;
     ax.L = L;
     ax.E = E;
-    ax.NB = L / E;
+    ax.NB = E ? L / E : 0;
+    const std::vector<int> gen = E ? std::vector<int>() : generic_radices(L);
     int rem = L, Ns = 1, s = 0;
     tw.clear();
     while (rem > 1) {
         if (s >= pspfft::kMaxStages) return false;
-        const int R = std::gcd(E, rem);
-        if (R <= 1) return false;
+        const int R = E ? std::gcd(E, rem) : gen[s];
+        if (R <= 1 || rem % R != 0) return false;
         ax.R[s] = R;
         ax.Ns[s] = Ns;
         ax.magic[s] = Ns > 1 ? static_cast<uint32_t>((uint64_t(1) << 32) / Ns + 1) : 0u;
-        if (Ns > 1) {  // verify the multiply-high division for every index used
+        if (E && Ns > 1) {  // verify the family kernels' multiply-high division for every index used
             for (uint32_t b = 0; b < static_cast<uint32_t>(L); ++b) {
                 const uint32_t q = static_cast<uint32_t>((uint64_t(b) * ax.magic[s]) >> 32);
                 if (q != b / static_cast<uint32_t>(Ns)) return false;
@@ -287,6 +326,7 @@ bool arrays_below_4gb(pspfft_plan_t p) {
 // the spectrum kz-fastest, and their z launches always take that kernel.
 bool z_wave_lines(pspfft_plan_t p) {
     const AxisPlan &az = p->host.ax[2];
+    if (az.E == 0) return false;  // generic kernel
     const int prec = p->host.prec, M = az.E & -az.E, NB = az.NB;
     const bool nb_ok = NB == 32 || NB == 64 || (NB == 16 && pspfft::wave_z_lds_bytes(prec, az.E, NB) > 80 * 1024);
     return az.nst == 3 && az.R[1] == M && nb_ok && M * az.R[2] == NB &&
@@ -306,12 +346,94 @@ void pass_lines(int mode, const int n[3], long &main, long &nyq) {
     }
 }
 
+// Lines per workgroup of the generic kernel for lines of up to L points: the
+// largest power of two up to 64 whose two LDS buffers fit 160 KB, with at most
+// max(L, 4096) points per workgroup (about 16 per thread).
+int generic_tile(int L, size_t csz) {
+    int t = 64;
+    while (t > 1 && (static_cast<size_t>(2) * t * (L + 1) * csz > 160 * 1024 ||
+                     static_cast<long>(t) * L > std::max(L, 4096)))
+        t /= 2;
+    return t;
+}
+
+// Grouped launches of a pass on the generic line kernel: one per precision (and
+// per kMaxProblems problems).  The launch's tile follows its longest line; a
+// line's arithmetic does not depend on the tile (each butterfly reads only its
+// own line), so results are the same alone and in any batch.
+pspfft_status launch_generic_lines(int mode, const std::vector<int> &all, const pspfft_plan_t *plans,
+                                   const pspfft_workspace_t *ws, const void *const *S, void *const *Phi,
+                                   hipStream_t stream) {
+    const int axis = pspfft::pass_axis(mode);
+    std::map<int, std::vector<int>> groups;
+    for (int i : all) groups[static_cast<int>(plans[i]->prec)].push_back(i);
+    for (auto &kv : groups) {
+        const int prec = kv.first;
+        const size_t csz = prec == 0 ? 8 : 16;
+        std::vector<int> idx = kv.second;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            return reinterpret_cast<uintptr_t>(plans[a]) < reinterpret_cast<uintptr_t>(plans[b]);
+        });
+        for (size_t c0 = 0; c0 < idx.size(); c0 += pspfft::kMaxProblems) {
+            const size_t c1 = std::min(idx.size(), c0 + pspfft::kMaxProblems);
+            LaunchArgs args;
+            std::memset(&args, 0, sizeof(args));
+            args.count = static_cast<int>(c1 - c0);
+            int lmax = 1;
+            for (size_t j = c0; j < c1; ++j) lmax = std::max(lmax, plans[idx[j]]->host.ax[axis].L);
+            for (size_t j = c0; j < c1; ++j) {
+                const int i = idx[j];
+                ProbArg &a = args.p[j - c0];
+                a.plan = plans[i]->dev;
+                a.S = S ? S[i] : nullptr;
+                a.Phi = Phi ? Phi[i] : nullptr;
+                a.W = ws[i]->W;
+                a.Wn = ws[i]->Wn;
+                if (j > c0 && plans[idx[j - 1]] == plans[i]) {
+                    args.seg[args.nseg - 1].group += 1;
+                    continue;
+                }
+                pspfft::Segment &sg = args.seg[args.nseg++];
+                sg.first = static_cast<int>(j - c0);
+                sg.group = 1;
+            }
+            args.gtile = generic_tile(lmax, csz);
+            long wg = 0;
+            for (int k = 0; k < args.nseg; ++k) {
+                pspfft::Segment &sg = args.seg[k];
+                const pspfft_plan_t pl = plans[idx[c0 + sg.first]];
+                long lm, ln;
+                pass_lines(mode, pl->n, lm, ln);
+                const long wm = (lm + args.gtile - 1) / args.gtile, wn = (ln + args.gtile - 1) / args.gtile;
+                sg.wg_begin = static_cast<int>(wg);
+                sg.wg_main = static_cast<int>(wm);
+                wg += (wm + wn) * sg.group;
+            }
+            if (wg > 0x7fffffffL) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+            args.nwg = static_cast<int>(wg);
+            const size_t lds = static_cast<size_t>(2) * args.gtile * (lmax + 1) * csz;
+            PSPFFT_LOG(3, "pass %d prec %d generic: %d problems in %d segments, %ld workgroups of 256 threads, "
+                          "%d lines each, %zu B LDS", mode, prec, args.count, args.nseg, wg, args.gtile, lds);
+            if (pspfft::launch_generic(mode, prec, args, static_cast<int>(wg), lds, stream) != hipSuccess)
+                return PSPFFT_ERR_DEVICE;
+        }
+    }
+    return PSPFFT_OK;
+}
+
 // Grouped launches of a line pass (X_FWD .. X_INV kernels) for the problems idx.
-pspfft_status launch_lines(int mode, const std::vector<int> &all, const pspfft_plan_t *plans,
+pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspfft_plan_t *plans,
                            const pspfft_workspace_t *ws, const void *const *S, void *const *Phi,
                            hipStream_t stream) {
     const int axis = pspfft::pass_axis(mode);
     const bool row = axis == 0;
+    // axes outside the radix families go to the generic kernel
+    std::vector<int> all, gen;
+    for (int i : all_in) (plans[i]->host.ax[axis].E ? all : gen).push_back(i);
+    if (!gen.empty()) {
+        const pspfft_status st = launch_generic_lines(mode, gen, plans, ws, S, Phi, stream);
+        if (st != PSPFFT_OK) return st;
+    }
     // One kernel per (precision, radix family E, last-stage radix K, spectrum layout).
     std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
     for (int i : all) {
@@ -567,7 +689,7 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
     // stage plans and twiddle tables (FP64, rounded once to the plan precision)
     for (int a = 0; a < 3; ++a) {
         std::vector<std::complex<double>> tw;
-        if (!build_axis(a, p->n[a], p->host.ax[a], tw)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+        if (!build_axis(a, p->n[a], prec, p->host.ax[a], tw)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
         const size_t tb = tw.size() * cs;
         pspfft_status st = alloc(&p->tw[a], tb);
         if (st != PSPFFT_OK) return st;
@@ -599,8 +721,8 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
             if (v >= 1 && v <= 16 && (v & (v - 1)) == 0) cap = v;
         }
         const int nbz = p->host.ax[2].NB;
-        int zb = 1;
-        while (zb < cap && nbz % (2 * zb) == 0) zb *= 2;
+        int zb = 1;  // generic z lines (NB = 0): no tiling, nz need not be a multiple of anything
+        while (nbz > 0 && zb < cap && nbz % (2 * zb) == 0) zb *= 2;
         p->host.zb = zb;
     }
     p->host.gz = z_wave_lines(p) ? 1 : 0;

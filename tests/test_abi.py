@@ -47,21 +47,39 @@ def test_status_strings(lib):
     assert lib.pspfft_status_string(99).decode() == "unknown status"
 
 
-@pytest.mark.parametrize("n,ok", [(8, True), (16, True), (128, True), (10, True), (12, True), (18, True),
-                                  (24, True), (36, True), (40, True), (48, True), (96, True), (144, True),
-                                  (1152, True), (2048, True), (4, False), (6, False), (9, False), (15, False),
-                                  (7, False), (27, False), (4096, False), (0, False), (-8, False)])
-def test_supported_sizes_y_z(lib, n, ok):
-    assert (lib.pspfft_workspace_bytes(16, n, 16, 0) > 0) == ok
-    assert (lib.pspfft_workspace_bytes(16, 16, n, 0) > 0) == ok
+def _smooth(n):
+    """n = 2^a 3^b 5^c"""
+    if n < 1:
+        return False
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
 
 
-@pytest.mark.parametrize("n,ok", [(16, True), (20, True), (24, True), (36, True), (32, True), (40, True),
-                                  (48, True), (72, True), (128, True), (2048, True), (4096, True), (2304, True),
-                                  (8, False), (10, False), (12, False), (18, False), (6, False), (8192, False)])
-def test_supported_sizes_x(lib, n, ok):
-    """x uses the packed real transform of length n, so its minimum sizes are twice those of y, z."""
-    assert (lib.pspfft_workspace_bytes(n, 16, 16, 0) > 0) == ok
+def _odd_part(n):
+    while n % 2 == 0:
+        n //= 2
+    return n
+
+
+def test_supported_sizes_y_z(lib):
+    """Every n = 2^a 3^b 5^c with 2n <= 4096, in both precisions, and nothing else."""
+    for n in list(range(-2, 2100)) + [2160, 2304, 3072, 4096]:
+        ok = _smooth(n) and n <= 2048
+        for prec in (0, 1):
+            assert (lib.pspfft_workspace_bytes(16, n, 16, prec) > 0) == ok, (n, prec)
+            assert (lib.pspfft_workspace_bytes(16, 16, n, prec) > 0) == ok, (n, prec)
+
+
+def test_supported_sizes_x(lib):
+    """x: every 2^a 3^b 5^c up to 2048 as for y and z; the packed real transform of
+    length n also takes longer rows whose odd part is 1, 3, 5 or 9 (up to 4096 in
+    FP32, 2304 in FP64)."""
+    for n in list(range(-2, 2100)) + [2160, 2304, 2400, 2560, 3072, 3200, 4096, 4608, 8192]:
+        for prec, lim in ((0, 4096), (1, 2304)):
+            ok = _smooth(n) and (n <= 2048 or (_odd_part(n) in (1, 3, 5, 9) and n <= lim))
+            assert (lib.pspfft_workspace_bytes(n, 16, 16, prec) > 0) == ok, (n, prec)
 
 
 def test_workspace_bytes_formula(lib):
@@ -72,10 +90,11 @@ def test_workspace_bytes_formula(lib):
             want = (main + 255) // 256 * 256 + (nyq + 255) // 256 * 256
             assert lib.pspfft_workspace_bytes(nx, ny, nz, prec) == want
     assert lib.pspfft_workspace_bytes(16, 16, 16, 7) == 0
-    # FP64 has a smaller maximum size
-    assert lib.pspfft_workspace_bytes(16, 2048, 8, 0) > 0
-    assert lib.pspfft_workspace_bytes(16, 2048, 8, 1) == 0
+    # odd sizes, and the largest rows per precision
+    assert lib.pspfft_workspace_bytes(15, 1, 27, 1) == ((27 * 2 * 15 * 16 + 255) // 256 + (27 * 2 * 16 + 255) // 256) * 256
+    assert lib.pspfft_workspace_bytes(16, 2048, 8, 1) > 0
     assert lib.pspfft_workspace_bytes(2304, 8, 8, 1) > 0
+    assert lib.pspfft_workspace_bytes(4096, 8, 8, 0) > 0
     assert lib.pspfft_workspace_bytes(4096, 8, 8, 1) == 0
 
 
@@ -97,7 +116,7 @@ def test_plan_create_rejects_bad_arguments_before_device_work(lib):
     assert st == 1
     st, handle = _create(lib, (0, 16, 16), (1, 1, 1))
     assert st == 1
-    for n in [(15, 16, 16), (16, 7, 16), (16, 16, 4096), (4, 16, 16), (8, 16, 16)]:
+    for n in [(7, 16, 16), (16, 7, 16), (16, 16, 4096), (22, 16, 16), (16, 16, 2049), (16, 14, 16)]:
         st, handle = _create(lib, n, (1, 1, 1))
         assert st == 2 and handle is None
     # null out-pointer
@@ -113,7 +132,7 @@ def test_plan_create_ex_rejects_unknown_flags_before_device_work(lib):
         assert handle.value is None
     assert lib.pspfft_plan_create_ex(16, 16, 16, h3, 0, 0, None) == 1
     assert lib.pspfft_plan_create_ex(16, 16, 16, None, 0, 1, ctypes.byref(handle)) == 1
-    assert lib.pspfft_plan_create_ex(16, 16, 15, h3, 0, 1, ctypes.byref(handle)) == 2
+    assert lib.pspfft_plan_create_ex(16, 16, 14, h3, 0, 1, ctypes.byref(handle)) == 2
 
 
 def test_null_handles(lib):
