@@ -34,13 +34,17 @@
  *
  * Errors.  Every call returns a pspfft_status.  Argument checks happen before
  * any work is enqueued; a failed check leaves nothing enqueued and nothing
- * allocated.  A failed kernel launch returns PSPFFT_ERR_DEVICE.
+ * allocated.  A failed kernel launch returns PSPFFT_ERR_DEVICE.  Failures are
+ * also reported as messages of level PSPFFT_CONSOLE_ERROR (see Messages).
  *
- * Supported sizes.  Each of nx, ny, nz must be 2^a * o with o in {1, 3, 5, 9};
- * ny, nz >= 8 (o = 1), 10 (o = 5), 12 (o = 3) or 18 (o = 9); nx, transformed in
- * packed real form, >= 16, 20, 24 or 36 respectively; ny, nz <= 2048 and
- * nx <= 4096 in FP32, ny, nz <= 1152 and nx <= 2304 in FP64.  Other sizes
- * return PSPFFT_ERR_UNSUPPORTED_SIZE.
+ * Supported sizes.  Each of nx, ny, nz may be any 2^a 3^b 5^c from 1 to 2048
+ * (2n <= 4096 points per doubled line), in both precisions.  Sizes 2^a * o with
+ * o in {1, 3, 5, 9} and n >= 8, 10, 12, 18 (x: twice that, the packed real
+ * transform having length n), up to 2048 (FP32) or 1152 (FP64) for y and z and
+ * 4096 or 2304 for x, run on compile-time radix-family kernels; the other sizes
+ * on a generic line kernel (slower; a plan that uses it reports a warning).
+ * Rows nx of 2560, 3072 and 4096 (FP32) or 2304 (FP64) are also accepted.
+ * Other sizes return PSPFFT_ERR_UNSUPPORTED_SIZE.
  * S and Phi must be aligned to two reals (8 bytes FP32, 16 bytes FP64).
  */
 #ifndef PSPFFT_H
@@ -97,6 +101,39 @@ typedef enum {
 pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspfft_precision prec,
                                  pspfft_plan_t *out);
 
+/*
+ * Messages (Sec. 3.2, the optional VerbosityOption of Create): levels in
+ * increasing verbosity.  The library prints messages of the level in force and
+ * below to stderr, each line prefixed "[pspfft <kind>]", or hands them to the
+ * callback set with pspfft_set_log_callback.  The process-wide level is
+ * PSPFFT_CONSOLE_ERROR unless the environment variable PSPFFT_LOG says
+ * error | warn | info1 | info2, or pspfft_set_verbosity changes it; a plan
+ * created with PSPFFT_PLAN_VERBOSITY(level) uses that level for its own
+ * messages.
+ *   ERROR    every failed call, with its reason
+ *   WARNING  conditions that cost speed (an axis on the generic line kernel)
+ *   INFO_1   one line per plan created (size, form of the passes, resident
+ *            bytes, workspace bytes) and per plan destroyed
+ *   INFO_2   the stage plan of each axis, and every kernel launch
+ */
+typedef enum {
+    PSPFFT_CONSOLE_ERROR = 0,
+    PSPFFT_CONSOLE_WARNING = 1,
+    PSPFFT_CONSOLE_INFO_1 = 2,
+    PSPFFT_CONSOLE_INFO_2 = 3
+} pspfft_verbosity;
+
+/* Set the process-wide level; an unknown level returns PSPFFT_ERR_INVALID_ARGUMENT. */
+pspfft_status pspfft_set_verbosity(pspfft_verbosity level);
+pspfft_verbosity pspfft_get_verbosity(void);
+
+/* Receiver of messages: level, the text (no newline; valid during the call) and
+ * the user pointer given to pspfft_set_log_callback.  May be called from any
+ * thread that calls the library, one message at a time. */
+typedef void (*pspfft_log_fn)(pspfft_verbosity level, const char *message, void *user);
+/* Send messages to fn instead of stderr; NULL goes back to stderr. */
+pspfft_status pspfft_set_log_callback(pspfft_log_fn fn, void *user);
+
 /* Plan options for pspfft_plan_create_ex. */
 typedef enum {
     PSPFFT_PLAN_DEFAULT = 0,
@@ -104,10 +141,15 @@ typedef enum {
      * of a plane could share one kernel. */
     PSPFFT_PLAN_FIVE_PASS = 1
 } pspfft_plan_flags;
+/* Option bits 4..6: the plan's own message level (the paper's VerbosityOption
+ * argument of Create), PSPFFT_PLAN_VERBOSITY(PSPFFT_CONSOLE_INFO_1) and so on. */
+#define PSPFFT_PLAN_VERBOSITY_SHIFT 4
+#define PSPFFT_PLAN_VERBOSITY(level) ((unsigned)((level) + 1) << PSPFFT_PLAN_VERBOSITY_SHIFT)
 
 /*
- * As pspfft_plan_create, with options (a bitwise or of pspfft_plan_flags;
- * unknown bits return PSPFFT_ERR_INVALID_ARGUMENT).  By default a plan fuses
+ * As pspfft_plan_create, with options (a bitwise or of pspfft_plan_flags and
+ * at most one PSPFFT_PLAN_VERBOSITY; unknown bits return
+ * PSPFFT_ERR_INVALID_ARGUMENT).  By default a plan fuses
  * the x and y transforms of each z plane when nx == ny = E*K (E in
  * {16, 20, 24, 36}, K a power of two dividing the power-of-two part of E, so at
  * most two stages) and the plane of x spectra fits in the 160 KB of LDS: FP32
@@ -144,17 +186,20 @@ int pspfft_plan_spectrum_kz_fastest(pspfft_plan_t plan);
  */
 int pspfft_workspace_ztile(pspfft_plan_t plan);
 
-/* Release a plan and everything it owns (Sec. 3.2, Destroy).  Synchronises the
- * device first.  NULL returns PSPFFT_ERR_INVALID_ARGUMENT. */
+/* Release a plan and everything it owns (Sec. 3.2, Destroy).  Waits for the
+ * kernels already launched for this plan (its last launch on each stream it
+ * ran on), not for other work on the device.  Workspaces created for the plan
+ * must be destroyed first.  NULL returns PSPFFT_ERR_INVALID_ARGUMENT. */
 pspfft_status pspfft_destroy(pspfft_plan_t plan);
 
 /*
  * Phi = potential of S (Sec. 3.2, Solve).  S and Phi: device arrays of nx*ny*nz
  * reals in the plan's precision, layout as above.  S == Phi is allowed (the
  * paper overwrites the source with the potential).  Uses the plan's default
- * workspace, so solves on one plan serialise on that workspace: concurrent
- * solves need a workspace each (pspfft_solve_ws).  Enqueues five kernels, or
- * three for a fused plan.
+ * workspace, allocated by the first call (PSPFFT_ERR_OUT_OF_MEMORY if that
+ * fails), so solves on one plan serialise on that workspace: concurrent solves
+ * need a workspace each (pspfft_solve_ws).  Enqueues five kernels, or three for
+ * a fused plan.
  */
 pspfft_status pspfft_solve(pspfft_plan_t plan, const void *S, void *Phi, hipStream_t stream);
 
@@ -167,7 +212,8 @@ pspfft_status pspfft_workspace_create(pspfft_plan_t plan, pspfft_workspace_t *ou
 pspfft_status pspfft_workspace_wrap(pspfft_plan_t plan, void *memory, size_t bytes,
                                     pspfft_workspace_t *out);
 
-/* Release a workspace handle (and its memory unless it was wrapped). */
+/* Release a workspace handle, and its memory unless it was wrapped (after the
+ * kernels launched so far for its plan have finished). */
 pspfft_status pspfft_workspace_destroy(pspfft_workspace_t ws);
 
 /* As pspfft_solve, with an explicit workspace created for the same plan. */
@@ -198,8 +244,16 @@ pspfft_status pspfft_pass_batched(pspfft_pass pass, int count, const pspfft_plan
                                   hipStream_t stream);
 
 /* Device bytes a plan keeps resident (Green's-function spectrum, twiddles,
- * plan tables, default workspace).  0 for NULL. */
+ * plan tables, and the default workspace once pspfft_solve has allocated it).
+ * 0 for NULL. */
 size_t pspfft_plan_bytes(pspfft_plan_t plan);
+
+/* Device bytes a plan of this size keeps resident once created, before its
+ * first pspfft_solve (spectrum octant, twiddle tables, plan table): what
+ * pspfft_plan_bytes returns for it.  Host-side arithmetic only; 0 for an
+ * unsupported size.  Lets a scheduler count a plan in its memory budget before
+ * creating it. */
+size_t pspfft_plan_resident_bytes(int nx, int ny, int nz, pspfft_precision prec);
 
 /* Bytes of one workspace: 2 ny nz (nx + 1) complex values of the precision.
  * 0 for an unsupported size. */

@@ -20,8 +20,13 @@ from . import _lib
 from ._lib import (PASS_NAMES, PASS_X_FWD, PASS_Y_FWD, PASS_Z_CONV, PASS_Y_INV, PASS_X_INV,  # noqa: F401
                    PspfftError)
 
-__all__ = ["Plan", "Workspace", "solve_batched", "pass_batched", "workspace_bytes", "PspfftError",
-           "PASS_NAMES", "PASS_X_FWD", "PASS_Y_FWD", "PASS_Z_CONV", "PASS_Y_INV", "PASS_X_INV"]
+from ._lib import CONSOLE_ERROR, CONSOLE_WARNING, CONSOLE_INFO_1, CONSOLE_INFO_2  # noqa: F401
+
+__all__ = ["Plan", "Workspace", "solve_batched", "pass_batched", "workspace_bytes", "plan_resident_bytes",
+           "PspfftError",
+           "PASS_NAMES", "PASS_X_FWD", "PASS_Y_FWD", "PASS_Z_CONV", "PASS_Y_INV", "PASS_X_INV",
+           "set_verbosity", "get_verbosity", "set_log_callback",
+           "CONSOLE_ERROR", "CONSOLE_WARNING", "CONSOLE_INFO_1", "CONSOLE_INFO_2"]
 
 
 def _prec(dtype) -> int:
@@ -42,7 +47,38 @@ def workspace_bytes(nx: int, ny: int, nz: int, dtype=torch.float32) -> int:
     return int(_lib.load().pspfft_workspace_bytes(nx, ny, nz, _prec(dtype)))
 
 
+def plan_resident_bytes(nx: int, ny: int, nz: int, dtype=torch.float32) -> int:
+    """``pspfft_plan_resident_bytes``: device bytes a plan of this size keeps."""
+    return int(_lib.load().pspfft_plan_resident_bytes(nx, ny, nz, _prec(dtype)))
+
+
 PLAN_FIVE_PASS = 1  # pspfft_plan_flags
+
+
+def set_verbosity(level: int) -> None:
+    """``pspfft_set_verbosity``: process-wide message level (Sec. 3.2, VerbosityOption)."""
+    _lib.check(_lib.load().pspfft_set_verbosity(int(level)), "pspfft_set_verbosity")
+
+
+def get_verbosity() -> int:
+    return int(_lib.load().pspfft_get_verbosity())
+
+
+_log_cb = None  # keeps the ctypes callback alive while the library holds it
+
+
+def set_log_callback(fn) -> None:
+    """``pspfft_set_log_callback``: ``fn(level, message)`` receives the library's
+    messages instead of stderr; ``None`` goes back to stderr."""
+    global _log_cb
+    lib = _lib.load()
+    if fn is None:
+        _lib.check(lib.pspfft_set_log_callback(ctypes.cast(None, _lib.LOG_FN), None), "pspfft_set_log_callback")
+        _log_cb = None
+        return
+    cb = _lib.LOG_FN(lambda level, msg, _user: fn(int(level), msg.decode(errors="replace")))
+    _lib.check(lib.pspfft_set_log_callback(cb, None), "pspfft_set_log_callback")
+    _log_cb = cb
 
 
 class Plan:
@@ -50,9 +86,12 @@ class Plan:
 
     ``five_pass=True`` keeps the five separate passes where the x and y
     transforms of a plane could otherwise share one kernel (``fused``).
+    ``verbosity`` (one of the CONSOLE_* levels) is the plan's own message level,
+    the paper's VerbosityOption of Create; by default the process-wide level.
     """
 
-    def __init__(self, nx: int, ny: int, nz: int, h, dtype=torch.float32, five_pass: bool = False):
+    def __init__(self, nx: int, ny: int, nz: int, h, dtype=torch.float32, five_pass: bool = False,
+                 verbosity: int | None = None):
         lib = _lib.load()
         if isinstance(h, (int, float)):
             h = (float(h),) * 3
@@ -63,6 +102,8 @@ class Plan:
         handle = ctypes.c_void_p()
         h3 = (ctypes.c_double * 3)(*self.h)
         flags = PLAN_FIVE_PASS if five_pass else 0
+        if verbosity is not None:
+            flags |= (int(verbosity) + 1) << _lib.PLAN_VERBOSITY_SHIFT
         _lib.check(lib.pspfft_plan_create_ex(int(nx), int(ny), int(nz), h3, _prec(dtype), flags,
                                              ctypes.byref(handle)),
                    f"pspfft_plan_create_ex({nx},{ny},{nz})")

@@ -37,9 +37,15 @@ EXPORTS = (
     "pspfft_destroy", "pspfft_solve",
     "pspfft_workspace_create", "pspfft_workspace_wrap", "pspfft_workspace_destroy",
     "pspfft_solve_ws", "pspfft_solve_batched", "pspfft_pass_batched",
-    "pspfft_plan_bytes", "pspfft_workspace_bytes", "pspfft_pass_bytes",
+    "pspfft_plan_bytes", "pspfft_plan_resident_bytes", "pspfft_workspace_bytes", "pspfft_pass_bytes",
     "pspfft_plan_info", "pspfft_plan_green", "pspfft_status_string",
+    "pspfft_set_verbosity", "pspfft_get_verbosity", "pspfft_set_log_callback",
 )
+
+# pspfft_verbosity (Sec. 3.2, VerbosityOption)
+CONSOLE_ERROR, CONSOLE_WARNING, CONSOLE_INFO_1, CONSOLE_INFO_2 = range(4)
+PLAN_VERBOSITY_SHIFT = 4
+LOG_FN = ctypes.CFUNCTYPE(None, ctypes.c_int, ctypes.c_char_p, ctypes.c_void_p)
 
 
 class PspfftError(RuntimeError):
@@ -87,10 +93,14 @@ def load():
         "pspfft_pass_batched": ([ip, ip, vpp, vpp, vpp, vpp, vp], ip),
         "pspfft_plan_bytes": ([vp], sz),
         "pspfft_workspace_bytes": ([ip, ip, ip, ip], sz),
+        "pspfft_plan_resident_bytes": ([ip, ip, ip, ip], sz),
         "pspfft_pass_bytes": ([vp, ip], sz),
         "pspfft_plan_info": ([vp, ctypes.POINTER(ctypes.c_int), dp, ctypes.POINTER(ctypes.c_int)], ip),
         "pspfft_plan_green": ([vp, vp, vp], ip),
         "pspfft_status_string": ([ip], ctypes.c_char_p),
+        "pspfft_set_verbosity": ([ip], ip),
+        "pspfft_get_verbosity": ([], ip),
+        "pspfft_set_log_callback": ([LOG_FN, vp], ip),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -5,15 +5,19 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdarg>
 #include <complex>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <new>
+#include <utility>
 #include <numeric>
 #include <vector>
 
@@ -33,11 +37,15 @@ struct pspfft_plan_s {
     DevPlan *dev = nullptr;  // device copy read by the kernels
     void *tw[3] = {nullptr, nullptr, nullptr};
     void *G = nullptr, *Gn = nullptr;
-    pspfft_workspace_t ws = nullptr;  // default workspace
-    size_t bytes = 0;
+    pspfft_workspace_t ws = nullptr;  // default workspace, allocated by the first pspfft_solve
+    size_t bytes = 0;        // resident bytes (without the default workspace)
     int device = 0;
     bool fused = false;      // x and y transforms of a z plane in one kernel
     int pE = 0, pK = 0;      // radix family and last radix of those kernels
+    int verbosity = -1;      // the plan's own message level (Sec. 3.2, VerbosityOption); -1: the process's
+    std::mutex mu;           // guards ws creation and `uses`
+    // the plan's last launch on each stream it ran on: what destroy waits for
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
 
 struct pspfft_workspace_s {
@@ -51,28 +59,67 @@ struct pspfft_workspace_s {
 
 namespace {
 
-int log_level() {
-    static int level = -1;
-    if (level < 0) {
-        const char *e = std::getenv("PSPFFT_LOG");
-        level = 0;
-        if (e) {
-            if (!std::strcmp(e, "warn")) level = 1;
-            else if (!std::strcmp(e, "info1")) level = 2;
-            else if (!std::strcmp(e, "info2")) level = 3;
-        }
+// ------------------------------------------------------------------ messages --
+// Levels of Sec. 3.2's VerbosityOption, least verbose first: errors (the
+// default), warnings, then two levels of information.  The process level starts
+// from PSPFFT_LOG (error | warn | info1 | info2) and is changed by
+// pspfft_set_verbosity; a plan created with a verbosity option keeps its own.
+// Messages go to stderr, or to the callback set with pspfft_set_log_callback.
+std::atomic<int> g_level{-1};
+std::mutex g_log_mu;
+pspfft_log_fn g_log_fn = nullptr;
+void *g_log_user = nullptr;
+
+int process_level() {
+    int l = g_level.load(std::memory_order_relaxed);
+    if (l >= 0) return l;
+    l = PSPFFT_CONSOLE_ERROR;
+    if (const char *e = std::getenv("PSPFFT_LOG")) {
+        if (!std::strcmp(e, "warn")) l = PSPFFT_CONSOLE_WARNING;
+        else if (!std::strcmp(e, "info1")) l = PSPFFT_CONSOLE_INFO_1;
+        else if (!std::strcmp(e, "info2")) l = PSPFFT_CONSOLE_INFO_2;
     }
-    return level;
+    int unset = -1;
+    g_level.compare_exchange_strong(unset, l);
+    return g_level.load(std::memory_order_relaxed);
 }
 
-#define PSPFFT_LOG(lvl, ...)                      \
-    do {                                          \
-        if (log_level() >= (lvl)) {               \
-            std::fprintf(stderr, "[pspfft] ");    \
-            std::fprintf(stderr, __VA_ARGS__);    \
-            std::fprintf(stderr, "\n");           \
-        }                                         \
+// Level in force for messages about a plan whose own level is `plan_level`.
+int level_for(int plan_level) { return plan_level >= 0 ? plan_level : process_level(); }
+
+void emit(int lvl, const char *fmt, ...) {
+    char buf[640];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    std::lock_guard<std::mutex> lk(g_log_mu);
+    if (g_log_fn) {
+        g_log_fn(static_cast<pspfft_verbosity>(lvl), buf, g_log_user);
+    } else {
+        static const char *const tag[4] = {"error", "warning", "info", "info"};
+        std::fprintf(stderr, "[pspfft %s] %s\n", tag[lvl & 3], buf);
+    }
+}
+
+#define PSPFFT_MSG(plan_level, lvl, ...)                                        \
+    do {                                                                        \
+        if (level_for(plan_level) >= (lvl)) emit((lvl), __VA_ARGS__);          \
     } while (0)
+#define PSPFFT_LOG(lvl, ...) PSPFFT_MSG(-1, lvl, __VA_ARGS__)
+
+// Report a failed call (level error) and return its status.
+pspfft_status fail(pspfft_status st, int plan_level, const char *fmt, ...) {
+    if (level_for(plan_level) >= PSPFFT_CONSOLE_ERROR) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        emit(PSPFFT_CONSOLE_ERROR, "%s: %s", buf, pspfft_status_string(st));
+    }
+    return st;
+}
 
 // Workgroup renumbering for the XCDs, per pass (0 none, 1 contiguous eighths,
 // 2 runs of 8 within blocks of 64).  PSPFFT_XCD_REMAP="abcde" overrides the
@@ -295,8 +342,33 @@ void ws_split(pspfft_workspace_t w, const int n[3], pspfft_precision prec) {
     w->Wn = static_cast<char *>(w->mem) + round_up(main, 256);
 }
 
+// Wait until every launch issued for plan p so far has finished (its last
+// launch on each stream it ran on), without waiting for other work.
+void wait_uses(pspfft_plan_t p) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (auto &u : p->uses) (void)hipEventSynchronize(u.second);
+}
+
+// Note that plan p has just been launched on `stream`.
+pspfft_status record_use(pspfft_plan_t p, hipStream_t stream) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (auto &u : p->uses)
+        if (u.first == stream) return hipEventRecord(u.second, stream) == hipSuccess ? PSPFFT_OK : PSPFFT_ERR_DEVICE;
+    if (p->uses.size() >= 64) {  // many short-lived streams: keep the list short
+        (void)hipEventSynchronize(p->uses.front().second);
+        (void)hipEventDestroy(p->uses.front().second);
+        p->uses.erase(p->uses.begin());
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return PSPFFT_ERR_DEVICE;
+    p->uses.emplace_back(stream, ev);
+    return hipEventRecord(ev, stream) == hipSuccess ? PSPFFT_OK : PSPFFT_ERR_DEVICE;
+}
+
 void destroy_plan(pspfft_plan_t p) {
     if (!p) return;
+    for (auto &u : p->uses) (void)hipEventDestroy(u.second);
+    p->uses.clear();
     if (p->ws) {
         if (p->ws->owned && p->ws->mem) (void)hipFree(p->ws->mem);
         delete p->ws;
@@ -605,20 +677,26 @@ pspfft_status launch_planes(bool fwd, const std::vector<int> &all, const pspfft_
 
 // One pass for `count` problems.  Plans with fused planes run their x and y
 // transforms together in X_FWD and X_INV and have nothing to do in Y_FWD and Y_INV.
+// track: note the launch stream per plan (what pspfft_destroy waits for); the
+// allocation-free solve creates no events and does not.
 pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
-                       const void *const *S, void *const *Phi, hipStream_t stream) {
-    if (count < 0) return PSPFFT_ERR_INVALID_ARGUMENT;
+                       const void *const *S, void *const *Phi, hipStream_t stream, bool track = true) {
+    const pspfft_status bad = PSPFFT_ERR_INVALID_ARGUMENT;
+    if (count < 0) return fail(bad, -1, "pass %d: negative count", mode);
     if (count == 0) return PSPFFT_OK;
-    if (!plans || !ws) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (mode == pspfft::X_FWD && !S) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (mode == pspfft::X_INV && !Phi) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (!plans || !ws) return fail(bad, -1, "pass %d: null plan or workspace array", mode);
+    if (mode == pspfft::X_FWD && !S) return fail(bad, -1, "pass %d: null source array", mode);
+    if (mode == pspfft::X_INV && !Phi) return fail(bad, -1, "pass %d: null potential array", mode);
     for (int i = 0; i < count; ++i) {
-        if (!plans[i] || !ws[i] || ws[i]->plan != plans[i]) return PSPFFT_ERR_INVALID_ARGUMENT;
+        if (!plans[i] || !ws[i] || ws[i]->plan != plans[i])
+            return fail(bad, plans[i] ? plans[i]->verbosity : -1, "pass %d: problem %d: null plan or workspace, or a "
+                        "workspace of another plan", mode, i);
         // the x passes move pairs of reals: S and Phi must be aligned to two reals
         const uintptr_t al = 2 * real_size(plans[i]->prec);
-        if (mode == pspfft::X_FWD && (!S[i] || reinterpret_cast<uintptr_t>(S[i]) % al)) return PSPFFT_ERR_INVALID_ARGUMENT;
+        if (mode == pspfft::X_FWD && (!S[i] || reinterpret_cast<uintptr_t>(S[i]) % al))
+            return fail(bad, plans[i]->verbosity, "pass %d: problem %d: source null or not aligned to two reals", mode, i);
         if (mode == pspfft::X_INV && (!Phi[i] || reinterpret_cast<uintptr_t>(Phi[i]) % al))
-            return PSPFFT_ERR_INVALID_ARGUMENT;
+            return fail(bad, plans[i]->verbosity, "pass %d: problem %d: potential null or not aligned to two reals", mode, i);
     }
     std::vector<int> lines, planes;
     for (int i = 0; i < count; ++i) {
@@ -628,8 +706,19 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
     pspfft_status st = PSPFFT_OK;
     if (!planes.empty()) st = launch_planes(mode == pspfft::X_FWD, planes, plans, ws, S, Phi, stream);
     if (st == PSPFFT_OK && !lines.empty()) st = launch_lines(mode, lines, plans, ws, S, Phi, stream);
+    if (st != PSPFFT_OK) return fail(st, plans[0]->verbosity, "pass %d of %d problems", mode, count);
+    // what destroying a plan (or one of its workspaces) must wait for
+    for (int i = 0; track && i < count && st == PSPFFT_OK; ++i) {
+        bool seen = false;
+        for (int j = 0; j < i && !seen; ++j) seen = plans[j] == plans[i];
+        if (!seen) st = record_use(plans[i], stream);
+    }
     return st;
 }
+
+
+pspfft_status solve_all(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws, const void *const *S,
+                        void *const *Phi, hipStream_t stream, bool track);
 
 }  // namespace
 
@@ -661,23 +750,35 @@ pspfft_status pspfft_plan_create(int nx, int ny, int nz, const double h[3], pspf
 
 pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], pspfft_precision prec,
                                     unsigned flags, pspfft_plan_t *out) {
-    if (!out || !h) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (flags & ~static_cast<unsigned>(PSPFFT_PLAN_FIVE_PASS)) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (prec != PSPFFT_FP32 && prec != PSPFFT_FP64) return PSPFFT_ERR_INVALID_ARGUMENT;
+    const unsigned vbits = (flags >> PSPFFT_PLAN_VERBOSITY_SHIFT) & 7u;
+    const int vlevel = vbits ? static_cast<int>(vbits) - 1 : -1;
+    const char *who = "pspfft_plan_create";
+    if (!out || !h) return fail(PSPFFT_ERR_INVALID_ARGUMENT, vlevel, "%s: null %s", who, !out ? "out" : "h");
+    if ((flags & ~(static_cast<unsigned>(PSPFFT_PLAN_FIVE_PASS) | (7u << PSPFFT_PLAN_VERBOSITY_SHIFT))) ||
+        vbits > PSPFFT_CONSOLE_INFO_2 + 1)
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, vlevel, "%s: unknown flags 0x%x", who, flags);
+    if (prec != PSPFFT_FP32 && prec != PSPFFT_FP64)
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, vlevel, "%s: unknown precision %d", who, static_cast<int>(prec));
     for (int a = 0; a < 3; ++a)
-        if (!(std::isfinite(h[a]) && h[a] > 0.0)) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (nx < 1 || ny < 1 || nz < 1) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (!sizes_ok(nx, ny, nz, prec)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+        if (!(std::isfinite(h[a]) && h[a] > 0.0))
+            return fail(PSPFFT_ERR_INVALID_ARGUMENT, vlevel, "%s: cell width h[%d] = %g is not finite and positive",
+                        who, a, h[a]);
+    if (nx < 1 || ny < 1 || nz < 1)
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, vlevel, "%s: mesh %d x %d x %d", who, nx, ny, nz);
+    if (!sizes_ok(nx, ny, nz, prec))
+        return fail(PSPFFT_ERR_UNSUPPORTED_SIZE, vlevel,
+                    "%s: mesh %d x %d x %d (each size must be 2^a 3^b 5^c, at most 2048; rows of up to %d with odd "
+                    "part 1, 3, 5 or 9)", who, nx, ny, nz, 2 * max_n(prec));
 
     pspfft_plan_t p = new (std::nothrow) pspfft_plan_s();
-    if (!p) return PSPFFT_ERR_OUT_OF_MEMORY;
+    if (!p) return fail(PSPFFT_ERR_OUT_OF_MEMORY, vlevel, "%s: host allocation", who);
     auto guard = make_guard([&] { destroy_plan(p); });
+    p->verbosity = vlevel;
     p->n[0] = nx;
     p->n[1] = ny;
     p->n[2] = nz;
     for (int a = 0; a < 3; ++a) p->h[a] = h[a];
     p->prec = prec;
-    if (hipGetDevice(&p->device) != hipSuccess) return PSPFFT_ERR_DEVICE;
     const size_t rs = real_size(prec), cs = cplx_size(prec);
     std::memset(&p->host, 0, sizeof(p->host));
     p->host.nx = nx;
@@ -685,14 +786,33 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
     p->host.nz = nz;
     p->host.prec = prec == PSPFFT_FP32 ? 0 : 1;
     size_t bytes = 0;
+    const char *pname = prec == PSPFFT_FP32 ? "fp32" : "fp64";
+    PSPFFT_MSG(vlevel, PSPFFT_CONSOLE_INFO_1, "creating plan %d x %d x %d %s, h = (%g, %g, %g)", nx, ny, nz, pname,
+               h[0], h[1], h[2]);
 
     // stage plans and twiddle tables (FP64, rounded once to the plan precision)
+    std::vector<std::complex<double>> tws[3];
     for (int a = 0; a < 3; ++a) {
-        std::vector<std::complex<double>> tw;
-        if (!build_axis(a, p->n[a], prec, p->host.ax[a], tw)) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+        if (!build_axis(a, p->n[a], prec, p->host.ax[a], tws[a]))
+            return fail(PSPFFT_ERR_UNSUPPORTED_SIZE, vlevel, "%s: no stage plan for axis %d (n = %d)", who, a,
+                        p->n[a]);
+        const AxisPlan &ax = p->host.ax[a];
+        char radices[96] = {0};
+        for (int s2 = 0, off = 0; s2 < ax.nst && off < 90; ++s2)
+            off += std::snprintf(radices + off, sizeof(radices) - off, s2 ? " x %d" : "%d", ax.R[s2]);
+        PSPFFT_MSG(vlevel, PSPFFT_CONSOLE_INFO_2, "  axis %c: n = %d, line of %d points, stages %s, %s", "xyz"[a],
+                   ax.n, ax.L, ax.nst ? radices : "none", ax.E ? "radix-family kernels" : "generic line kernel");
+        if (!ax.E)
+            PSPFFT_MSG(vlevel, PSPFFT_CONSOLE_WARNING,
+                       "plan %d x %d x %d %s: axis %c (n = %d) runs on the generic line kernel, slower than the "
+                       "radix families (n = 2^a times 1, 3, 5 or 9)", nx, ny, nz, pname, "xyz"[a], ax.n);
+    }
+    if (hipGetDevice(&p->device) != hipSuccess) return fail(PSPFFT_ERR_DEVICE, vlevel, "%s: hipGetDevice", who);
+    for (int a = 0; a < 3; ++a) {
+        const std::vector<std::complex<double>> &tw = tws[a];
         const size_t tb = tw.size() * cs;
         pspfft_status st = alloc(&p->tw[a], tb);
-        if (st != PSPFFT_OK) return st;
+        if (st != PSPFFT_OK) return fail(st, vlevel, "%s: twiddle table of %zu bytes", who, tb);
         std::vector<unsigned char> buf(tb);
         for (size_t i = 0; i < tw.size(); ++i) {
             if (prec == PSPFFT_FP32) {
@@ -703,7 +823,8 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
                 std::memcpy(&buf[i * cs], v, sizeof(v));
             }
         }
-        if (hipMemcpy(p->tw[a], buf.data(), tb, hipMemcpyHostToDevice) != hipSuccess) return PSPFFT_ERR_DEVICE;
+        if (hipMemcpy(p->tw[a], buf.data(), tb, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(PSPFFT_ERR_DEVICE, vlevel, "%s: twiddle upload", who);
         p->host.ax[a].tw = p->tw[a];
         p->host.ax[a].post = a == 0 ? static_cast<char *>(p->tw[a]) + p->host.ax[a].ntw * cs : nullptr;
         bytes += tb;
@@ -743,8 +864,8 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
     const size_t gmain = static_cast<size_t>(nz + 1) * (ny + 1) * nx * rs;
     const size_t gnyq = static_cast<size_t>(nz + 1) * (ny + 1) * rs;
     pspfft_status st;
-    if ((st = alloc(&p->G, gmain)) != PSPFFT_OK) return st;
-    if ((st = alloc(&p->Gn, gnyq)) != PSPFFT_OK) return st;
+    if ((st = alloc(&p->G, gmain)) != PSPFFT_OK || (st = alloc(&p->Gn, gnyq)) != PSPFFT_OK)
+        return fail(st, vlevel, "%s: spectrum of %zu bytes", who, gmain + gnyq);
     bytes += gmain + gnyq;
     {
         void *a = nullptr, *b = nullptr, *cx = nullptr, *cy = nullptr, *cz = nullptr;
@@ -754,70 +875,64 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
             for (void *q : {a, b, cx, cy, cz})
                 if (q) (void)hipFree(q);
         });
-        if ((st = alloc(&a, oct * sizeof(double))) != PSPFFT_OK) return st;
-        if ((st = alloc(&b, oct * sizeof(double))) != PSPFFT_OK) return st;
         const std::vector<double> tx = cos_table(nx), ty = cos_table(ny), tz = cos_table(nz);
-        if ((st = alloc(&cx, tx.size() * sizeof(double))) != PSPFFT_OK) return st;
-        if ((st = alloc(&cy, ty.size() * sizeof(double))) != PSPFFT_OK) return st;
-        if ((st = alloc(&cz, tz.size() * sizeof(double))) != PSPFFT_OK) return st;
+        if ((st = alloc(&a, oct * sizeof(double))) != PSPFFT_OK || (st = alloc(&b, oct * sizeof(double))) != PSPFFT_OK ||
+            (st = alloc(&cx, tx.size() * sizeof(double))) != PSPFFT_OK ||
+            (st = alloc(&cy, ty.size() * sizeof(double))) != PSPFFT_OK ||
+            (st = alloc(&cz, tz.size() * sizeof(double))) != PSPFFT_OK)
+            return fail(st, vlevel, "%s: FP64 spectrum scratch of %zu bytes", who, 2 * oct * sizeof(double));
         if (hipMemcpy(cx, tx.data(), tx.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(cy, ty.data(), ty.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(cz, tz.data(), tz.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-            return PSPFFT_ERR_DEVICE;
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PSPFFT_ERR_DEVICE;
-        if (pspfft::green_spectrum(nx, ny, nz, p->h, p->host.prec, p->host.gz, static_cast<double *>(a),
-                                   static_cast<double *>(b),
-                                   static_cast<const double *>(cx), static_cast<const double *>(cy),
-                                   static_cast<const double *>(cz), p->G, p->Gn, s) != hipSuccess)
-            return PSPFFT_ERR_DEVICE;
-        if (hipStreamSynchronize(s) != hipSuccess) return PSPFFT_ERR_DEVICE;
+            hipMemcpy(cz, tz.data(), tz.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+            pspfft::green_spectrum(nx, ny, nz, p->h, p->host.prec, p->host.gz, static_cast<double *>(a),
+                                   static_cast<double *>(b), static_cast<const double *>(cx),
+                                   static_cast<const double *>(cy), static_cast<const double *>(cz), p->G, p->Gn,
+                                   s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(PSPFFT_ERR_DEVICE, vlevel, "%s: spectrum of the doubled Green's function", who);
     }
     p->host.G = p->G;
     p->host.Gn = p->Gn;
 
     void *dv = nullptr;
-    if ((st = alloc(&dv, sizeof(DevPlan))) != PSPFFT_OK) return st;
+    if ((st = alloc(&dv, sizeof(DevPlan))) != PSPFFT_OK) return fail(st, vlevel, "%s: plan table", who);
     p->dev = static_cast<DevPlan *>(dv);
-    if (hipMemcpy(p->dev, &p->host, sizeof(DevPlan), hipMemcpyHostToDevice) != hipSuccess) return PSPFFT_ERR_DEVICE;
+    if (hipMemcpy(p->dev, &p->host, sizeof(DevPlan), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(PSPFFT_ERR_DEVICE, vlevel, "%s: plan table upload", who);
     bytes += sizeof(DevPlan);
+    p->bytes = bytes;  // the default workspace comes with the first pspfft_solve
 
-    // default workspace
-    p->ws = new (std::nothrow) pspfft_workspace_s();
-    if (!p->ws) return PSPFFT_ERR_OUT_OF_MEMORY;
-    p->ws->plan = p;
-    p->ws->owned = true;
-    p->ws->mem = nullptr;
-    p->ws->bytes = ws_bytes(p->n, prec);
-    if ((st = alloc(&p->ws->mem, p->ws->bytes)) != PSPFFT_OK) return st;
-    ws_split(p->ws, p->n, prec);
-    bytes += p->ws->bytes;
-    p->bytes = bytes;
-
-    PSPFFT_LOG(2, "plan %dx%dx%d %s: %zu bytes resident, %s", nx, ny, nz, prec == PSPFFT_FP32 ? "fp32" : "fp64",
-               bytes, p->fused ? "fused x-y planes" : "five passes");
+    PSPFFT_MSG(vlevel, PSPFFT_CONSOLE_INFO_1,
+               "plan %d x %d x %d %s: %zu bytes resident, %s, spectrum %s, workspace %zu bytes per solve "
+               "(z tile %d)", nx, ny, nz, pname, bytes, p->fused ? "fused x-y planes" : "five passes",
+               p->host.gz ? "kz-fastest" : "kx-fastest", ws_bytes(p->n, prec), p->host.zb);
     guard.armed = false;
     *out = p;
     return PSPFFT_OK;
 }
 
 pspfft_status pspfft_destroy(pspfft_plan_t plan) {
-    if (!plan) return PSPFFT_ERR_INVALID_ARGUMENT;
-    (void)hipDeviceSynchronize();
+    if (!plan) return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_destroy: null plan");
+    // wait for this plan's own launches only, not for the whole device
+    wait_uses(plan);
+    PSPFFT_MSG(plan->verbosity, PSPFFT_CONSOLE_INFO_1, "destroying plan %d x %d x %d %s", plan->n[0], plan->n[1],
+               plan->n[2], plan->prec == PSPFFT_FP32 ? "fp32" : "fp64");
     destroy_plan(plan);
     return PSPFFT_OK;
 }
 
 pspfft_status pspfft_workspace_create(pspfft_plan_t plan, pspfft_workspace_t *out) {
-    if (!plan || !out) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (!plan || !out) return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan ? plan->verbosity : -1, "pspfft_workspace_create: null argument");
     pspfft_workspace_t w = new (std::nothrow) pspfft_workspace_s();
-    if (!w) return PSPFFT_ERR_OUT_OF_MEMORY;
+    if (!w) return fail(PSPFFT_ERR_OUT_OF_MEMORY, plan->verbosity, "pspfft_workspace_create: host allocation");
     w->plan = plan;
     w->owned = true;
     w->bytes = ws_bytes(plan->n, plan->prec);
     pspfft_status st = alloc(&w->mem, w->bytes);
     if (st != PSPFFT_OK) {
         delete w;
-        return st;
+        return fail(st, plan->verbosity, "pspfft_workspace_create: %zu bytes", ws_bytes(plan->n, plan->prec));
     }
     ws_split(w, plan->n, plan->prec);
     *out = w;
@@ -825,11 +940,14 @@ pspfft_status pspfft_workspace_create(pspfft_plan_t plan, pspfft_workspace_t *ou
 }
 
 pspfft_status pspfft_workspace_wrap(pspfft_plan_t plan, void *memory, size_t bytes, pspfft_workspace_t *out) {
-    if (!plan || !memory || !out) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (bytes < ws_bytes(plan->n, plan->prec)) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (reinterpret_cast<uintptr_t>(memory) % 256 != 0) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (!plan || !memory || !out) return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan ? plan->verbosity : -1, "pspfft_workspace_wrap: null argument");
+    if (bytes < ws_bytes(plan->n, plan->prec))
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan->verbosity, "pspfft_workspace_wrap: %zu bytes, the plan needs %zu",
+                    bytes, ws_bytes(plan->n, plan->prec));
+    if (reinterpret_cast<uintptr_t>(memory) % 256 != 0)
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan->verbosity, "pspfft_workspace_wrap: memory not 256-byte aligned");
     pspfft_workspace_t w = new (std::nothrow) pspfft_workspace_s();
-    if (!w) return PSPFFT_ERR_OUT_OF_MEMORY;
+    if (!w) return fail(PSPFFT_ERR_OUT_OF_MEMORY, plan->verbosity, "pspfft_workspace_wrap: host allocation");
     w->plan = plan;
     w->owned = false;
     w->mem = memory;
@@ -840,10 +958,12 @@ pspfft_status pspfft_workspace_wrap(pspfft_plan_t plan, void *memory, size_t byt
 }
 
 pspfft_status pspfft_workspace_destroy(pspfft_workspace_t ws) {
-    if (!ws) return PSPFFT_ERR_INVALID_ARGUMENT;
-    if (ws->plan && ws == ws->plan->ws) return PSPFFT_ERR_INVALID_ARGUMENT;  // owned by its plan
+    if (!ws) return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_workspace_destroy: null workspace");
+    if (ws->plan && ws == ws->plan->ws)
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, ws->plan->verbosity,
+                    "pspfft_workspace_destroy: the plan's default workspace goes with the plan");
     if (ws->owned && ws->mem) {
-        (void)hipDeviceSynchronize();
+        wait_uses(ws->plan);  // launches of its plan, the only ones that can use it
         (void)hipFree(ws->mem);
     }
     delete ws;
@@ -853,35 +973,88 @@ pspfft_status pspfft_workspace_destroy(pspfft_workspace_t ws) {
 pspfft_status pspfft_pass_batched(pspfft_pass pass, int count, const pspfft_plan_t *plans,
                                   const pspfft_workspace_t *ws, const void *const *S, void *const *Phi,
                                   hipStream_t stream) {
-    if (pass < PSPFFT_PASS_X_FWD || pass > PSPFFT_PASS_X_INV) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (pass < PSPFFT_PASS_X_FWD || pass > PSPFFT_PASS_X_INV)
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_pass_batched: unknown pass %d", static_cast<int>(pass));
     return run_pass(static_cast<int>(pass), count, plans, ws, S, Phi, stream);
 }
 
 pspfft_status pspfft_solve_batched(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
                                    const void *const *S, void *const *Phi, hipStream_t stream) {
-    if (count < 0 || (count > 0 && (!plans || !ws || !S || !Phi))) return PSPFFT_ERR_INVALID_ARGUMENT;
+    return solve_all(count, plans, ws, S, Phi, stream, true);
+}
+
+}  // extern "C"
+
+namespace {
+pspfft_status solve_all(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws, const void *const *S,
+                        void *const *Phi, hipStream_t stream, bool track) {
+    if (count < 0 || (count > 0 && (!plans || !ws || !S || !Phi)))
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_solve_batched: count %d or null array", count);
     for (int i = 0; i < count; ++i)
         for (int j = i + 1; j < count; ++j)
-            if (ws[i] == ws[j]) return PSPFFT_ERR_INVALID_ARGUMENT;
+            if (ws[i] == ws[j])
+                return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_solve_batched: problems %d and %d share a workspace", i, j);
     for (int mode = pspfft::X_FWD; mode <= pspfft::X_INV; ++mode) {
-        pspfft_status st = run_pass(mode, count, plans, ws, S, Phi, stream);
+        pspfft_status st = run_pass(mode, count, plans, ws, S, Phi, stream, track);
         if (st != PSPFFT_OK) return st;
     }
     return PSPFFT_OK;
 }
+}  // namespace
+
+extern "C" {
 
 pspfft_status pspfft_solve_ws(pspfft_plan_t plan, pspfft_workspace_t ws, const void *S, void *Phi,
                               hipStream_t stream) {
-    if (!plan || !ws || !S || !Phi) return PSPFFT_ERR_INVALID_ARGUMENT;
+    if (!plan || !ws || !S || !Phi) return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan ? plan->verbosity : -1, "pspfft_solve_ws: null argument");
     return pspfft_solve_batched(1, &plan, &ws, &S, &Phi, stream);
 }
 
 pspfft_status pspfft_solve(pspfft_plan_t plan, const void *S, void *Phi, hipStream_t stream) {
-    if (!plan || !S || !Phi) return PSPFFT_ERR_INVALID_ARGUMENT;
-    return pspfft_solve_ws(plan, plan->ws, S, Phi, stream);
+    if (!plan || !S || !Phi) return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan ? plan->verbosity : -1, "pspfft_solve: null argument");
+    pspfft_workspace_t ws;
+    {
+        std::lock_guard<std::mutex> lk(plan->mu);
+        if (!plan->ws) {  // the default workspace, on first use
+            pspfft_workspace_t w = new (std::nothrow) pspfft_workspace_s();
+            if (!w) return fail(PSPFFT_ERR_OUT_OF_MEMORY, plan->verbosity, "pspfft_solve: host allocation");
+            w->plan = plan;
+            w->owned = true;
+            w->bytes = ws_bytes(plan->n, plan->prec);
+            const pspfft_status st = alloc(&w->mem, w->bytes);
+            if (st != PSPFFT_OK) {
+                delete w;
+                return fail(st, plan->verbosity, "pspfft_solve: default workspace of %zu bytes", ws_bytes(plan->n, plan->prec));
+            }
+            ws_split(w, plan->n, plan->prec);
+            plan->ws = w;
+        }
+        ws = plan->ws;
+    }
+    return pspfft_solve_ws(plan, ws, S, Phi, stream);
 }
 
-size_t pspfft_plan_bytes(pspfft_plan_t plan) { return plan ? plan->bytes : 0; }
+size_t pspfft_plan_resident_bytes(int nx, int ny, int nz, pspfft_precision prec) {
+    if (prec != PSPFFT_FP32 && prec != PSPFFT_FP64) return 0;
+    if (!sizes_ok(nx, ny, nz, prec)) return 0;
+    const int n[3] = {nx, ny, nz};
+    size_t bytes = sizeof(DevPlan);
+    for (int a = 0; a < 3; ++a) {  // twiddle tables, as pspfft_plan_create builds them
+        AxisPlan ax;
+        std::vector<std::complex<double>> tw;
+        if (!build_axis(a, n[a], prec, ax, tw)) return 0;
+        bytes += tw.size() * cplx_size(prec);
+    }
+    // spectrum octant: main part and the kx = nx column
+    bytes += static_cast<size_t>(nz + 1) * (ny + 1) * (nx + 1) * real_size(prec);
+    return bytes;
+}
+
+size_t pspfft_plan_bytes(pspfft_plan_t plan) {
+    if (!plan) return 0;
+    std::lock_guard<std::mutex> lk(plan->mu);
+    return plan->bytes + (plan->ws ? plan->ws->bytes : 0);
+}
 
 size_t pspfft_pass_bytes(pspfft_plan_t plan, pspfft_pass pass) {
     if (!plan) return 0;
@@ -923,6 +1096,22 @@ pspfft_status pspfft_plan_info(pspfft_plan_t plan, int dims[3], double h[3], psp
     return PSPFFT_OK;
 }
 
+pspfft_status pspfft_set_verbosity(pspfft_verbosity level) {
+    if (level < PSPFFT_CONSOLE_ERROR || level > PSPFFT_CONSOLE_INFO_2)
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_set_verbosity: unknown level %d", static_cast<int>(level));
+    g_level.store(static_cast<int>(level), std::memory_order_relaxed);
+    return PSPFFT_OK;
+}
+
+pspfft_verbosity pspfft_get_verbosity(void) { return static_cast<pspfft_verbosity>(process_level()); }
+
+pspfft_status pspfft_set_log_callback(pspfft_log_fn fn, void *user) {
+    std::lock_guard<std::mutex> lk(g_log_mu);
+    g_log_fn = fn;
+    g_log_user = fn ? user : nullptr;
+    return PSPFFT_OK;
+}
+
 pspfft_status pspfft_plan_green(pspfft_plan_t plan, void *dst, hipStream_t stream) {
     if (!plan || !dst) return PSPFFT_ERR_INVALID_ARGUMENT;
     if (pspfft::green_export(plan->n[0], plan->n[1], plan->n[2], plan->host.prec, plan->host.gz, plan->G, plan->Gn,
@@ -932,3 +1121,21 @@ pspfft_status pspfft_plan_green(pspfft_plan_t plan, void *dst, hipStream_t strea
 }
 
 }  // extern "C"
+
+namespace pspfft {
+// One solve with `bytes` bytes of device memory at `mem` (256-byte aligned) as
+// its workspace, through a workspace handle on the stack: allocates nothing.
+pspfft_status solve_on(pspfft_plan_t plan, void *mem, size_t bytes, const void *S, void *Phi, hipStream_t stream) {
+    if (!plan || !mem || !S || !Phi) return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan ? plan->verbosity : -1, "solve: null argument");
+    if (bytes < ws_bytes(plan->n, plan->prec) || reinterpret_cast<uintptr_t>(mem) % 256 != 0)
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan->verbosity, "solve: workspace memory too small or misaligned");
+    pspfft_workspace_s w;  // a handle on the stack: no allocation
+    w.plan = plan;
+    w.owned = false;
+    w.mem = mem;
+    w.bytes = bytes;
+    ws_split(&w, plan->n, plan->prec);
+    pspfft_workspace_t wp = &w;
+    return solve_all(1, &plan, &wp, &S, &Phi, stream, false);
+}
+}  // namespace pspfft

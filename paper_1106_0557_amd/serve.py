@@ -51,6 +51,7 @@ class Request:
     _ws: Any = None
     _ptrs: Any = None            # executor's cached launch arguments while admitted
     _dep: Any = None             # executor's record of the launch this request was last in
+    _ready: Any = None           # executor's mark, at admission, of the caller's work before the first pass
 
     @property
     def latency(self) -> float:
@@ -120,6 +121,15 @@ class GpuExecutor:
     def resident_bytes(self) -> int:
         return sum(p.resident_bytes for p in self.plans.values())
 
+    def has_plan(self, req: Request) -> bool:
+        return self.key(req) in self.plans
+
+    def plan_bytes(self, req: Request) -> int:
+        """Device bytes the plan of this request's mesh keeps resident (spectrum,
+        twiddles, tables), known before the plan is created."""
+        nx, ny, nz = req.n
+        return self.ps.plan_resident_bytes(nx, ny, nz, self.dtype)
+
     # ------------------------------------------------ workspaces, outputs
     def acquire(self, req: Request):
         k = self.key(req)
@@ -153,6 +163,14 @@ class GpuExecutor:
     def alloc_output(self, req: Request):
         return self.torch.empty(req.S.shape, dtype=self.dtype, device=req.S.device)
 
+    def admitted(self, req: Request) -> None:
+        """Mark the caller's stream at admission: the source was produced there,
+        and the workspace and output were allocated there.  The request's first
+        launch, on a stream of the pool, waits for this mark."""
+        ev = self._event()
+        ev.record(self.torch.cuda.current_stream(self.device))
+        req._ready = ev
+
     # ------------------------------------------------------------ launches
     def begin_step(self) -> None:
         self._launches = 0
@@ -174,6 +192,10 @@ class GpuExecutor:
         waited = set()
         cols = ([], [], [], [])
         for r in reqs:
+            if r._ready is not None:  # first launch: after the caller's work on its stream
+                s.wait_event(r._ready)
+                self._step_events.append(r._ready)  # recycled with this step's events
+                r._ready = None
             if r._dep is not None:
                 ev, step = r._dep
                 if step in self._pending and id(ev) not in waited:
@@ -224,9 +246,10 @@ class Server:
     """Admission by memory footprint + pass-level continuous batching.
 
     ``budget_bytes`` bounds the device memory of in-flight requests (workspace
-    and output) plus idle pooled workspaces; resident plans are not counted (they
-    are shared and long-lived).  ``max_inflight`` bounds the requests on the
-    device, ``max_steps_ahead`` the scheduler steps enqueued but not finished.
+    and output), idle pooled workspaces and the resident plans (spectrum and
+    twiddles, one per mesh size, kept once created).  ``max_inflight`` bounds the
+    requests on the device, ``max_steps_ahead`` the scheduler steps enqueued but
+    not finished.
     """
 
     def __init__(self, executor, budget_bytes: int, max_inflight: int = 64, max_steps_ahead: int = 16,
@@ -239,7 +262,8 @@ class Server:
         self.waiting: collections.deque = collections.deque()
         self.inflight: List[Request] = []
         self.finished: List[Request] = []
-        self.used = executor.pooled_bytes()  # idle workspaces already held by the executor
+        # idle workspaces and plans already held by the executor
+        self.used = executor.pooled_bytes() + executor.resident_bytes()
         self.steps: collections.deque = collections.deque()  # (token, requests completing in it)
         self.t0 = clock()
         self.launches = 0
@@ -253,8 +277,11 @@ class Server:
     def footprint(self, req: Request) -> int:
         return self.ex.workspace_bytes(req) + self.ex.output_bytes(req)
 
+    def _plan_need(self, req: Request) -> int:
+        return 0 if self.ex.has_plan(req) else self.ex.plan_bytes(req)
+
     def submit(self, req: Request) -> None:
-        if self.footprint(req) > self.budget:
+        if self.footprint(req) + self._plan_need(req) > self.budget:
             req.rejected = True
             req.done = True
             req.error = "footprint exceeds the memory budget"
@@ -267,7 +294,7 @@ class Server:
         while self.waiting and len(self.inflight) < self.max_inflight:
             req = self.waiting[0]
             reuse = self.ex.has_pooled(req)
-            need = self.ex.output_bytes(req) + (0 if reuse else self.ex.workspace_bytes(req))
+            need = self.ex.output_bytes(req) + (0 if reuse else self.ex.workspace_bytes(req)) + self._plan_need(req)
             if self.used + need > self.budget:
                 # idle pooled workspaces of other sizes give way to a waiting request
                 pooled = self.ex.pooled_bytes()
@@ -276,8 +303,11 @@ class Server:
                 else:
                     break
             self.waiting.popleft()
-            req._ws = self.ex.acquire(req)
+            req._ws = self.ex.acquire(req)  # creates the plan if it is new; it stays counted in `used`
             req.phi = self.ex.alloc_output(req)
+            admitted = getattr(self.ex, "admitted", None)
+            if admitted is not None:
+                admitted(req)
             self.used += need
             self.max_used = max(self.max_used, self.used)
             active = getattr(self.ex, "active_passes", None)

@@ -148,3 +148,50 @@ def test_served_small_budget_defers_but_serves_all():
     for r in served[:3]:
         ref = oracle.solve_fft(r.S.double().cpu().numpy(), r.h)
         assert norms.rel_l2(r.phi.double().cpu().numpy(), ref) <= 1e-5
+
+
+def test_warm_server_waits_for_a_source_produced_just_before_submit():
+    """A server whose plans, workspaces and streams are warm takes a source that
+    the caller's stream is still producing (a long chain of kernels queued just
+    before submit): the first pass must wait for it."""
+    from paper_1106_0557_amd.serve import GpuExecutor, Request, Server
+
+    say("[serve] fresh source into a warm server")
+    n = 64
+    ex = GpuExecutor(dtype=torch.float32)
+    warm = [Request(i, (n, n, n), (1.0 / n,) * 3, torch.zeros((n, n, n), device="cuda")) for i in range(4)]
+    Server(ex, budget_bytes=1 << 34, max_inflight=4).run_trace(warm, realtime=False)
+    ex.synchronize()
+    base = sources.random_field(n, seed=77).to("cuda", torch.float32)
+    reqs = []
+    for i in range(3):
+        S = torch.zeros_like(base)
+        # queue enough work on the current stream that the source is still being
+        # written when the request's first pass could start
+        big = torch.randn(2048, 2048, device="cuda")
+        for _ in range(20):
+            big = big @ big
+            big = big / big.norm()
+        S += base * (i + 1) + 0.0 * big[0, 0]
+        reqs.append(Request(i, (n, n, n), (1.0 / n,) * 3, S))
+    fin = Server(ex, budget_bytes=1 << 34, max_inflight=4).run_trace(reqs, realtime=False)
+    ex.synchronize()
+    ref = oracle.solve_fft(base.double().cpu().numpy(), 1.0 / n)
+    for r in sorted(fin, key=lambda q: q.index):
+        got = r.phi.double().cpu().numpy() / (r.index + 1)
+        assert norms.rel_l2(got, ref) <= 1e-5, f"request {r.index} read its source before it was written"
+
+
+def test_plan_bytes_before_and_after_the_first_solve():
+    """pspfft_plan_resident_bytes tells the plan's bytes before it exists; the
+    default workspace is allocated by the first pspfft_solve and counted then."""
+    import paper_1106_0557_amd as ps
+
+    for n, dt in (((64, 64, 64), torch.float32), ((60, 48, 30), torch.float64), ((16, 8, 512), torch.float32)):
+        want = ps.plan_resident_bytes(*n, dt)
+        p = ps.Plan(*n, h=0.1, dtype=dt)
+        assert p.resident_bytes == want
+        p.solve(torch.zeros(n[::-1], dtype=dt, device="cuda"))
+        torch.cuda.synchronize()
+        assert p.resident_bytes == want + p.workspace_bytes
+        p.close()

@@ -33,8 +33,23 @@ class FakeExecutor:
         self.fused_sizes = set(fused_sizes)  # meshes whose plans skip the y passes
         self.pool = {}
         self.log = []          # (step, pass, request index)
+        self.events = []       # ("admit" | "pass", request index), in call order
         self.step_no = 0
         self.created = 0
+        self.plans = set()     # meshes with a resident plan
+
+    def plan_bytes(self, req):
+        nx, ny, nz = req.n
+        return 32 * (nx + 1) * (ny + 1) * (nz + 1)
+
+    def has_plan(self, req):
+        return self.key(req) in self.plans
+
+    def resident_bytes(self):
+        return sum(32 * (n[0] + 1) * (n[1] + 1) * (n[2] + 1) for (n, _) in self.plans)
+
+    def admitted(self, req):
+        self.events.append(("admit", req.index))
 
     def workspace_bytes(self, req):
         nx, ny, nz = req.n
@@ -57,6 +72,7 @@ class FakeExecutor:
         return sum(b for lst in self.pool.values() for (_, b) in lst)
 
     def acquire(self, req):
+        self.plans.add(self.key(req))
         lst = self.pool.get(self.key(req))
         if lst:
             return lst.pop()
@@ -80,6 +96,7 @@ class FakeExecutor:
     def run_pass(self, p, reqs):
         for r in reqs:
             self.log.append((self.step_no, p, r.index))
+            self.events.append(("pass", r.index))
             if p == NUM_PASSES - 1 and self.compute:
                 r.phi = oracle.solve_fft(r.S, r.h)
 
@@ -135,8 +152,9 @@ def test_fused_requests_skip_the_y_passes_beside_five_pass_ones():
 
 def test_admission_respects_budget_and_slots():
     ex = FakeExecutor()
-    one = ex.workspace_bytes(_reqs([32])[0]) + ex.output_bytes(_reqs([32])[0])
-    srv = Server(ex, budget_bytes=3 * one + 10, max_inflight=8)
+    r32 = _reqs([32])[0]
+    one = ex.workspace_bytes(r32) + ex.output_bytes(r32)
+    srv = Server(ex, budget_bytes=3 * one + ex.plan_bytes(r32) + 10, max_inflight=8)
     fin = srv.run_trace(_reqs([32] * 10), realtime=False)
     assert all(r.done for r in fin)
     assert srv.max_used <= srv.budget
@@ -158,7 +176,7 @@ def test_admission_respects_budget_and_slots():
 def test_oversized_request_is_rejected_not_deadlocked():
     ex = FakeExecutor()
     small = _reqs([16])[0]
-    budget = ex.workspace_bytes(small) + ex.output_bytes(small)
+    budget = ex.workspace_bytes(small) + ex.output_bytes(small) + ex.plan_bytes(small)
     srv = Server(ex, budget_bytes=budget, max_inflight=4)
     fin = srv.run_trace(_reqs([16, 64, 16]), realtime=False)
     rej = [r for r in fin if r.rejected]
@@ -231,9 +249,9 @@ def test_pool_reuse_and_trim():
     assert ex.created <= 2 * (1 + srv.max_steps_ahead) and ex.created < 6
     # a budget that only fits after idle workspaces of another size are released
     r64 = _reqs([64])[0]
-    budget = ex.workspace_bytes(r64) + ex.output_bytes(r64) + 1
+    budget = ex.workspace_bytes(r64) + ex.output_bytes(r64) + ex.plan_bytes(r64) + ex.resident_bytes() + 1
     srv2 = Server(ex, budget_bytes=budget, max_inflight=2)
-    assert srv2.used == ex.pooled_bytes() > 0
+    assert srv2.used == ex.pooled_bytes() + ex.resident_bytes() and ex.pooled_bytes() > 0
     fin = srv2.run_trace([Request(9, (64, 64, 64), (1 / 64,) * 3, None)], realtime=False)
     assert fin[0].done and not fin[0].rejected
 
@@ -251,3 +269,43 @@ def test_results_through_the_scheduler_match_the_oracle():
         assert norms.rel_l2(r.phi, want) < 1e-12
     s = summarize(fin, 1.0)
     assert s["served"] == 4 and s["rejected"] == 0 and np.isfinite(s["latency_ms_p99"])
+
+
+def test_plan_bytes_count_in_the_budget():
+    """A plan (spectrum and twiddles) is resident from its first request on and
+    takes budget like any other device memory."""
+    ex = FakeExecutor()
+    r = _reqs([32])[0]
+    one = ex.workspace_bytes(r) + ex.output_bytes(r)
+    P = ex.plan_bytes(r)
+    assert P > one  # so that the test tells the two accountings apart
+    # room for the plan and two requests: never three in flight
+    srv = Server(ex, budget_bytes=P + 2 * one + 10, max_inflight=8)
+    fin = srv.run_trace(_reqs([32] * 8), realtime=False)
+    assert all(r.done and not r.rejected for r in fin)
+    assert srv.max_used <= srv.budget and srv.max_used >= P + one
+    by_step = {}
+    for st, p, i in ex.log:
+        by_step.setdefault(st, set()).add(i)
+    assert max(len(v) for v in by_step.values()) == 2
+    # a request whose plan alone would overflow the budget is rejected up front
+    ex2 = FakeExecutor()
+    srv2 = Server(ex2, budget_bytes=one + P - 1, max_inflight=8)
+    fin2 = srv2.run_trace(_reqs([32]), realtime=False)
+    assert fin2[0].rejected and not ex2.plans
+    # a server starting on an executor that already holds plans counts them
+    srv3 = Server(ex, budget_bytes=1 << 40)
+    assert srv3.used == ex.resident_bytes() + ex.pooled_bytes() >= P
+
+
+def test_each_request_is_marked_at_admission_before_its_first_pass():
+    """The executor marks the caller's stream when a request is admitted (its
+    source, workspace and output are ready there); the first pass comes after."""
+    ex = FakeExecutor(fused_sizes=(16,))
+    srv = Server(ex, budget_bytes=1 << 40, max_inflight=3)
+    fin = srv.run_trace(_reqs([16, 24, 16, 32, 16, 24]), realtime=False)
+    assert all(r.done for r in fin)
+    for i in range(6):
+        seq = [k for k, (what, r) in enumerate(ex.events) if r == i]
+        kinds = [ex.events[k][0] for k in seq]
+        assert kinds[0] == "admit" and kinds.count("admit") == 1 and "pass" in kinds[1:]

@@ -1,0 +1,98 @@
+"""Message levels (Sec. 3.2: the optional VerbosityOption of Create, levels
+CONSOLE_INFO_2 > CONSOLE_INFO_1 > CONSOLE_WARNING > CONSOLE_ERROR, default ERROR).
+
+Runs without a GPU: the messages checked here are emitted before any device
+work (argument checks, stage plans), or by the device step that fails here.
+"""
+import ctypes
+
+import pytest
+
+import paper_1106_0557_amd as ps
+from paper_1106_0557_amd import _lib
+
+
+@pytest.fixture()
+def captured():
+    lib = _lib.load()
+    before = lib.pspfft_get_verbosity()
+    msgs = []
+    ps.set_log_callback(lambda level, text: msgs.append((level, text)))
+    yield msgs
+    ps.set_log_callback(None)
+    ps.set_verbosity(before)
+
+
+def _create(n, flags=0, prec=0):
+    lib = _lib.load()
+    h3 = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    handle = ctypes.c_void_p()
+    st = lib.pspfft_plan_create_ex(n[0], n[1], n[2], h3, prec, flags, ctypes.byref(handle))
+    if st == 0:  # on a GPU the plan exists: release it
+        assert lib.pspfft_destroy(handle.value) == 0
+    return st
+
+
+def _levels(msgs):
+    return [lvl for lvl, _ in msgs]
+
+
+def test_default_level_is_error():
+    assert ps.get_verbosity() in (ps.CONSOLE_ERROR, ps.CONSOLE_WARNING, ps.CONSOLE_INFO_1, ps.CONSOLE_INFO_2)
+
+
+def test_error_level_reports_only_failures(captured):
+    ps.set_verbosity(ps.CONSOLE_ERROR)
+    assert _create((16, 7, 16)) == 2  # 7 is not 2^a 3^b 5^c
+    assert _levels(captured) == [ps.CONSOLE_ERROR]
+    assert "16 x 7 x 16" in captured[0][1] and "unsupported mesh size" in captured[0][1]
+    captured.clear()
+    _create((15, 16, 16))  # valid; a generic x axis is only a warning
+    assert all(lvl == ps.CONSOLE_ERROR for lvl in _levels(captured))
+
+
+@pytest.mark.parametrize("level", [ps.CONSOLE_WARNING, ps.CONSOLE_INFO_1, ps.CONSOLE_INFO_2])
+def test_each_level_adds_its_messages(captured, level):
+    ps.set_verbosity(level)
+    _create((15, 16, 24))
+    levels = _levels(captured)
+    assert max(levels) == level
+    # the generic x axis (n = 15) is a warning at every level from WARNING on
+    warn = [t for lvl, t in captured if lvl == ps.CONSOLE_WARNING]
+    assert len(warn) == 1 and "axis x" in warn[0] and "generic line kernel" in warn[0]
+    info1 = [t for lvl, t in captured if lvl == ps.CONSOLE_INFO_1]
+    info2 = [t for lvl, t in captured if lvl == ps.CONSOLE_INFO_2]
+    if level >= ps.CONSOLE_INFO_1:
+        assert info1 and info1[0].startswith("creating plan 15 x 16 x 24 fp32")
+    else:
+        assert not info1
+    if level >= ps.CONSOLE_INFO_2:
+        # one stage-plan line per axis: x = 15 points (5 x 3), y = 32 (16 x 2), z = 48 (24 x 2)
+        assert len(info2) >= 3
+        assert "axis x: n = 15, line of 15 points, stages 5 x 3, generic line kernel" in info2[0]
+        assert "axis y: n = 16, line of 32 points, stages 16 x 2, radix-family kernels" in info2[1]
+        assert "axis z: n = 24, line of 48 points, stages 24 x 2, radix-family kernels" in info2[2]
+    else:
+        assert not info2
+
+
+def test_plan_option_overrides_the_process_level(captured):
+    ps.set_verbosity(ps.CONSOLE_ERROR)
+    _create((15, 16, 24), flags=(ps.CONSOLE_INFO_2 + 1) << _lib.PLAN_VERBOSITY_SHIFT)
+    assert ps.CONSOLE_INFO_2 in _levels(captured) and ps.CONSOLE_WARNING in _levels(captured)
+    captured.clear()
+    # and a quiet plan under a verbose process level prints nothing but errors
+    ps.set_verbosity(ps.CONSOLE_INFO_2)
+    _create((15, 16, 24), flags=(ps.CONSOLE_ERROR + 1) << _lib.PLAN_VERBOSITY_SHIFT)
+    assert all(lvl == ps.CONSOLE_ERROR for lvl in _levels(captured))
+
+
+def test_bad_levels_are_rejected(captured):
+    lib = _lib.load()
+    ps.set_verbosity(ps.CONSOLE_ERROR)
+    assert lib.pspfft_set_verbosity(4) == 1
+    assert lib.pspfft_set_verbosity(-1) == 1
+    assert lib.pspfft_get_verbosity() == ps.CONSOLE_ERROR
+    # a plan level beyond INFO_2 is an unknown option
+    assert _create((16, 16, 16), flags=5 << _lib.PLAN_VERBOSITY_SHIFT) == 1
+    assert _levels(captured)[-1] == ps.CONSOLE_ERROR
