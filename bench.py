@@ -219,6 +219,35 @@ def main():
     lat64 = [evs64[i].elapsed_time(evs64[i + 1]) for i in range(R)]
     solves64 = R / wall64
     eff64 = algorithmic_bytes(n, 8) * solves64 / 1e9
+    # one FP64 solve's working set (workspace, source, potential, spectrum) fits
+    # the 256 MB Infinity Cache; the same solves rotating over 4 plans and 4
+    # source/potential pairs (4 times that) do not
+    ws64 = plan64.workspace_bytes + 2 * S64_dev.numel() * 8 + ps.plan_resident_bytes(n, n, n, torch.float64)
+    rot_plans = [ps.Plan(n, n, n, h=h, dtype=torch.float64) for _ in range(4)]
+    rot_S = [S64_dev.clone() for _ in range(4)]
+    rot_P = [torch.empty_like(S64_dev) for _ in range(4)]
+    for k in range(8):
+        rot_plans[k % 4].solve(rot_S[k % 4], out=rot_P[k % 4])
+    torch.cuda.synchronize()
+    Rr = max(100, R // 5)
+    evr = [torch.cuda.Event(enable_timing=True) for _ in range(Rr + 1)]
+    t0 = time.perf_counter()
+    evr[0].record(stream)
+    for i in range(Rr):
+        rot_plans[i % 4].solve(rot_S[i % 4], out=rot_P[i % 4])
+        evr[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall_r = time.perf_counter() - t0
+    lat_r = [evr[i].elapsed_time(evr[i + 1]) for i in range(Rr)]
+    for pl in rot_plans:
+        pl.close()
+    del rot_S, rot_P
+    fp64_rot = {"solves_per_s": round(Rr / wall_r, 2),
+                "effective_GBps_B_model": round(algorithmic_bytes(n, 8) * Rr / wall_r / 1e9, 1),
+                "moved_GBps": round(plan64.solve_bytes() * Rr / wall_r / 1e9, 1),
+                "latency_ms_p50": round(percentile(lat_r, 50), 5),
+                "latency_ms_p99": round(percentile(lat_r, 99), 5), "solves_timed": Rr,
+                "working_set_bytes": 4 * ws64}
 
     # --------------------------------- single large solve, 512^3 (context)
     large = None
@@ -320,20 +349,63 @@ def main():
 
         log("[bench] cpu oracle sample")
         S_np = S64.numpy()
-        times = []
-        ref = None
-        t_start = time.perf_counter()
-        while True:
+        all_threads = oracle.threads()
+
+        def timed(fn, budget_s, min_reps=1, max_reps=20):
+            times = []
+            t_start = time.perf_counter()
+            while len(times) < max_reps:
+                t0 = time.perf_counter()
+                out = fn()
+                times.append(time.perf_counter() - t0)
+                if len(times) >= min_reps and time.perf_counter() - t_start + times[-1] > budget_s:
+                    break
+            return out, times
+
+        ref, times = timed(lambda: oracle.solve_fft(S_np, h), args.cpu_seconds * 0.2, min_reps=2)
+        c2_all = len(times) / sum(times)
+        n1, h1, S1 = sources.config1()
+        S1 = S1.numpy()
+        _, t1 = timed(lambda: oracle.solve_fft(S1, h1), 1.0, min_reps=3)
+        c1_all = len(t1) / sum(t1)
+        batch3 = sources.config3()
+        t0 = time.perf_counter()
+        for nn, src in batch3:
+            oracle.solve_fft(src.numpy(), 1.0 / nn)
+        c3_s = time.perf_counter() - t0
+        c4 = {}
+        trace4 = sources.config4_trace(rate_hz=0, count=40)
+        for size in sources.CONFIG4_SIZES:
+            r4 = next(r for r in trace4 if r.n == size)
+            S4 = sources.blob_field(size, r4.blobs).numpy()
             t0 = time.perf_counter()
-            ref = oracle.solve_fft(S_np, h)
-            times.append(time.perf_counter() - t0)
-            if time.perf_counter() - t_start + times[-1] > args.cpu_seconds or len(times) >= 20:
-                break
-        cpu = {"value": len(times) / sum(times), "unit": "solves/s", "cores": oracle.threads(),
-               "kind": "oracle",
-               "sample": f"{len(times)} full FP64 oracle solves (naive mixed-radix FFT convolution on the "
-                         f"{2 * n}^3 padded mesh, OpenMP) of the same {n}^3 spheroid source",
-               "cpu_model": platform.processor() or platform.machine()}
+            oracle.solve_fft(S4, 1.0 / size)
+            c4[str(size)] = round(1.0 / (time.perf_counter() - t0), 4)
+        oracle.set_threads(1)
+        try:
+            _, t1s = timed(lambda: oracle.solve_fft(S1, h1), 1.0, min_reps=2)
+            _, t2s = timed(lambda: oracle.solve_fft(S_np, h), 0.0, min_reps=1, max_reps=1)
+        finally:
+            oracle.set_threads(all_threads)
+        model = platform.processor() or platform.machine()
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+        cpu = {"value": round(c2_all, 4), "unit": "solves/s", "cores": all_threads, "kind": "oracle",
+               "sample": f"{len(times)} FP64 oracle solves (naive mixed-radix FFT convolution on the {2 * n}^3 "
+                         f"padded mesh, OpenMP on {all_threads} threads) of the same {n}^3 spheroid source; "
+                         f"beside it the configurations below",
+               "cpu_model": model, "os_cpu_count": os.cpu_count(), "omp_threads": all_threads,
+               "config2_solves_per_s": {"all_threads": round(c2_all, 4), "one_thread": round(1.0 / t2s[0], 4)},
+               "config1_solves_per_s": {"all_threads": round(c1_all, 3), "one_thread": round(len(t1s) / sum(t1s), 3)},
+               "config3_batch_s_all_threads": round(c3_s, 3),
+               "config3_solves_per_s_all_threads": round(len(batch3) / c3_s, 3),
+               "config4_sizes_solves_per_s_all_threads": c4}
         acc32["rel_l2_vs_oracle"] = norms.rel_l2(P_list[0].double().cpu().numpy(), ref)
         acc32["rel_max_vs_oracle"] = norms.rel_max(P_list[0].double().cpu().numpy(), ref)
         o64 = out64.cpu().numpy()
@@ -359,22 +431,27 @@ def main():
                                f"spheroid a=0.3 b=0.15, S=4pi inside), FP32 served path, {B} solves per step "
                                f"in grouped launches",
                    "n": n, "padded": 2 * n, "batch_per_step": B, "parallelism": "single-gpu"},
-        "effective_GBps": round(eff32, 1),
-        "copy_ceiling_GBps": round(copy_gbs, 1),
-        "roofline_frac_effective": round(eff32 / HBM_PEAK_GBS, 4),
-        "algorithmic_bytes_per_solve": bytes32,
-        "fused_xy_planes": plan32.fused,
         "bytes_moved_per_solve": plan32.solve_bytes(),
         "moved_GBps": round(plan32.solve_bytes() * solves32 / 1e9, 1),
+        "moved_frac_of_peak": round(plan32.solve_bytes() * solves32 / 1e9 / HBM_PEAK_GBS, 4),
+        "copy_ceiling_GBps": round(copy_gbs, 1),
+        "fused_xy_planes": plan32.fused,
+        "b_model": {"effective_GBps": round(eff32, 1), "bytes_per_solve": bytes32,
+                    "note": "five-pass byte model B(n) = 2r n^3 + 12c n^2(n+1) + r(n+1)^3: a fixed yardstick of "
+                            "solves/s, not bytes moved (the fused path moves bytes_moved_per_solve)"},
         "step_ms_p50": round(percentile(step_ms, 50), 5),
         "step_ms_p99": round(percentile(step_ms, 99), 5),
         "pass_ms_avg": {pass_names[p]: round(avg_pass[p], 5) for p in active},
         "fp32_accuracy": acc32,
-        "fp64_plain": {"solves_per_s": round(solves64, 2), "effective_GBps": round(eff64, 1),
-                       "roofline_frac_effective": round(eff64 / HBM_PEAK_GBS, 4),
+        "fp64_plain": {"solves_per_s": round(solves64, 2), "effective_GBps_B_model": round(eff64, 1),
+                       "moved_GBps": round(plan64.solve_bytes() * solves64 / 1e9, 1),
                        "latency_ms_p50": round(percentile(lat64, 50), 5),
                        "latency_ms_p99": round(percentile(lat64, 99), 5),
-                       "solves_timed": R, "accuracy": acc64},
+                       "solves_timed": R, "accuracy": acc64,
+                       "working_set_bytes": ws64,
+                       "note": "one plan, one source: the working set fits the 256 MB Infinity Cache (MALL), "
+                               "so this is not an HBM figure; rotating_4_plans is",
+                       "rotating_4_plans": fp64_rot},
         "roofline": {"bound": "hbm",
                      "kernel": f"{'plane_kernel' if pass_names[dom] in ('xy_fwd', 'yx_inv') else 'pass_kernel'} "
                                f"({pass_names[dom]})",

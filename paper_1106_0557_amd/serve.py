@@ -424,81 +424,184 @@ def summarize(finished: Sequence[Request], wall: float) -> dict:
     }
 
 
-def source_pool(sizes, per_size: int, seed: int, dtype, device="cuda"):
-    """Gaussian-blob sources per mesh size, generated once and kept on the device."""
-    import numpy as np
-
+def trace_sources(trace, dtype, device="cuda"):
+    """Each trace request's own Gaussian-blob source on its n^3 unit-box mesh,
+    generated on the device before any timing starts."""
     from . import sources
 
-    rng = np.random.default_rng(seed)
-    pool = {}
-    for n in sizes:
-        pool[n] = [sources.blob_field(n, sources.draw_blobs(rng, 8), device=device).to(dtype)
-                   for _ in range(per_size)]
-    return pool
+    return [sources.blob_field(r.n, r.blobs, device=device).to(dtype) for r in trace]
+
+
+def replay_plain(sizes_arrivals, srcs, dtype=None, realtime=True, log=print):
+    """The plain path under the same load: the requests' solves issued one after
+    another with ``pspfft_solve`` (one plan and its default workspace per mesh
+    size) as they arrive, on one stream.  Latency is arrival to completion; a
+    solve starts when it has arrived and the one before it is enqueued."""
+    import torch
+
+    import paper_1106_0557_amd as ps
+
+    dtype = dtype or torch.float64
+    plans, outs = {}, {}
+    for (n, _), S in zip(sizes_arrivals, srcs):
+        if n not in plans:
+            plans[n] = ps.Plan(n, n, n, h=1.0 / n, dtype=dtype)
+            outs[n] = torch.empty_like(S)
+            plans[n].solve(S, out=outs[n])  # warm: kernels, default workspace
+    torch.cuda.synchronize()
+    pool = [torch.cuda.Event() for _ in range(256)]
+    pending = collections.deque()
+    lat = []
+    t0 = time.perf_counter()
+
+    def poll():
+        while pending and pending[0][1].query():
+            _, ev, arrival = pending.popleft()
+            lat.append(time.perf_counter() - t0 - arrival)
+            pool.append(ev)
+
+    for i, ((n, arrival), S) in enumerate(zip(sizes_arrivals, srcs)):
+        while realtime and time.perf_counter() - t0 < arrival:
+            poll()
+        plans[n].solve(S, out=outs[n])
+        ev = pool.pop() if pool else torch.cuda.Event()
+        ev.record()
+        pending.append((i, ev, arrival if realtime else 0.0))
+        poll()
+    while pending:
+        pending[0][1].synchronize()
+        poll()
+    wall = time.perf_counter() - t0
+    for p in plans.values():
+        p.close()
+    lat_ms = [v * 1e3 for v in lat]
+    return {"requests": len(lat), "solves_per_s": len(lat) / wall, "latency_ms_p50": percentile(lat_ms, 50),
+            "latency_ms_p99": percentile(lat_ms, 99), "latency_ms_max": max(lat_ms), "wall_s": wall}
 
 
 def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, count: int = 2000,
-                 budget_frac: float = 0.8, max_inflight: int = 64):
-    """Served-path measurement: closed-loop saturation, then a Poisson trace at
-    0.7 x saturation; reports solves/s and p50/p99 latency for the n^3 stream
-    and for the mixed-size stream of ``sizes``.  64 requests in flight keep
-    about 20 per pass launch (three passes per fused plan); measured, 32 gives
-    4 % (single size) and 10 % (config-4 mix) less, 96 no more."""
+                 budget_frac: float = 0.8, max_inflight: int = 64, small_budget: int = 2 << 30,
+                 plain_dtype=None):
+    """Served-path measurement on two request streams, the n^3 stream and the
+    mixed-size stream of ``sizes`` (weights ``weights``, seed 4), each request
+    with its own Gaussian-blob source:
+
+    * closed-loop saturation (every request present at t = 0);
+    * Poisson arrivals at 0.7 x saturation: solves/s and p50/p99 arrival-to-
+      completion latency;
+    * the same arrivals under a forced small memory budget (``small_budget``
+      bytes), so that admission defers requests;
+    * the same arrivals through the plain path in ``plain_dtype`` (FP64), one
+      ``pspfft_solve`` after another;
+    * the potential of one request per size against the FP64 GPU solve.
+
+    64 requests in flight keep about 20 per pass launch (three passes per fused
+    plan); measured, 32 gives 4 % (single size) and 10 % (config-4 mix) less, 96
+    no more."""
     import torch
 
     from . import sources
 
     dtype = dtype or torch.float32
-    free, total = torch.cuda.mem_get_info()
-    budget = int(budget_frac * free)
+    plain_dtype = plain_dtype or torch.float64
     results = {}
     streams = {"single": ((n,), (1.0,)),
                "mix": (tuple(sizes or sources.CONFIG4_SIZES), tuple(weights or sources.CONFIG4_WEIGHTS))}
     for name, (szs, wts) in streams.items():
-        pool = source_pool(szs, 4, seed=4, dtype=dtype)
+        # sizes, blobs and unit-rate gaps: scaling the gaps by 1 / rate gives the
+        # Poisson arrivals at that rate (same draws)
+        trace = sources.config4_trace(rate_hz=1.0, count=count, sizes=szs, weights=wts)
+        srcs = trace_sources(trace, dtype)
+        torch.cuda.synchronize()
+        free, _ = torch.cuda.mem_get_info()
+        budget = int(budget_frac * free)
         ex = GpuExecutor(dtype=dtype)
 
-        def make(reqs_spec):
-            out = []
-            for i, (t, nn) in enumerate(reqs_spec):
-                S = pool[nn][i % len(pool[nn])]
-                out.append(Request(i, (nn, nn, nn), (1.0 / nn,) * 3, S, arrival=t))
-            return out
+        def make(scale, idx=None):
+            idx = range(len(trace)) if idx is None else idx
+            return [Request(i, (trace[i].n,) * 3, (1.0 / trace[i].n,) * 3, srcs[i], arrival=trace[i].arrival * scale)
+                    for i in idx]
 
         # warm plans, kernels and the workspace pool (a server does this at start-up)
+        first = {}
+        for i, r in enumerate(trace):
+            first.setdefault(r.n, i)
         warm = Server(ex, budget, max_inflight=max_inflight)
-        warm.run_trace(make([(0.0, s) for _ in range(4 * max_inflight) for s in szs]), realtime=False)
+        warm.run_trace(make(0.0, [first[s] for _ in range(4 * max_inflight // len(szs) + 1) for s in szs]),
+                       realtime=False)
         ex.synchronize()
         # closed loop: all requests present at t = 0
-        trace = sources.config4_trace(rate_hz=0, count=count, sizes=szs, weights=wts)
         srv = Server(ex, budget, max_inflight=max_inflight)
-        reqs = make([(0.0, r.n) for r in trace])  # the clients' side, before the clock starts
+        reqs = make(0.0)  # the clients' side, before the clock starts
         t0 = time.perf_counter()
         fin = srv.run_trace(reqs, realtime=False)
         ex.synchronize()
         wall = time.perf_counter() - t0
         sat = summarize(fin, wall)
+        # accuracy: the first request of each size against the FP64 GPU solve
+        import paper_1106_0557_amd as ps
+
+        acc = {}
+        for s, i in sorted(first.items()):
+            r = next(q for q in fin if q.index == i)
+            p64 = ps.Plan(s, s, s, h=1.0 / s, dtype=torch.float64)
+            ref = p64.solve(srcs[i].to(torch.float64))
+            d = r.phi.double() - ref
+            acc[str(s)] = {"rel_l2_vs_gpu_fp64": float(d.norm() / ref.norm()),
+                           "rel_max_vs_gpu_fp64": float(d.abs().max() / ref.abs().max())}
+            p64.close()
+            del ref, d
+        del fin, reqs
         log(f"[serve] {name}: saturation {sat['solves_per_s']:.0f} solves/s, {srv.launches} launches, "
             f"max batch {srv.max_batch}")
         # open loop: Poisson arrivals at 0.7 x saturation
         rate = 0.7 * sat["solves_per_s"]
-        trace = sources.config4_trace(rate_hz=rate, count=count, sizes=szs, weights=wts)
         srv = Server(ex, budget, max_inflight=max_inflight)
-        reqs = make([(r.arrival, r.n) for r in trace])
+        reqs = make(1.0 / rate)
         t0 = time.perf_counter()
         fin = srv.run_trace(reqs, realtime=True)
         ex.synchronize()
-        wall = time.perf_counter() - t0
-        op = summarize(fin, wall)
+        op = summarize(fin, time.perf_counter() - t0)
+        del fin, reqs
         log(f"[serve] {name}: Poisson {rate:.0f}/s: p50 {op['latency_ms_p50']:.3f} ms, "
             f"p99 {op['latency_ms_p99']:.3f} ms")
-        results[name] = {"sizes": list(szs), "weights": list(wts), "saturation": sat,
-                         "poisson_rate_hz": rate, "poisson": op, "budget_bytes": budget,
-                         "max_inflight": max_inflight}
+        # the same arrivals under a small memory budget (idle pooled workspaces
+        # beyond it are released first)
+        ex.trim_pool()
+        torch.cuda.synchronize()
+        srv = Server(ex, small_budget, max_inflight=max_inflight)
+        reqs = make(1.0 / rate)
+        t0 = time.perf_counter()
+        fin = srv.run_trace(reqs, realtime=True)
+        ex.synchronize()
+        small = summarize(fin, time.perf_counter() - t0)
+        small.update({"budget_bytes": small_budget, "max_used_bytes": srv.max_used})
+        del fin, reqs
+        log(f"[serve] {name}: budget {small_budget >> 20} MiB: {small['solves_per_s']:.0f} solves/s, "
+            f"p50 {small['latency_ms_p50']:.3f} ms, p99 {small['latency_ms_p99']:.3f} ms, "
+            f"max used {srv.max_used >> 20} MiB")
         for lst in ex.pool.values():
             for ws in lst:
                 ws.close()
+        ex.pool.clear()
         for p in ex.plans.values():
             p.close()
+        ex.plans.clear()
+        # the plain path (FP64, one solve after another) under the same arrivals
+        srcs64 = [S.to(plain_dtype) for S in srcs]
+        del srcs
+        torch.cuda.synchronize()
+        arrivals = [(r.n, r.arrival / rate) for r in trace]
+        plain = replay_plain(arrivals, srcs64, dtype=plain_dtype, realtime=True)
+        log(f"[serve] {name}: plain {str(plain_dtype).split('.')[-1]} at {rate:.0f}/s: "
+            f"{plain['solves_per_s']:.0f} solves/s, p50 {plain['latency_ms_p50']:.3f} ms, "
+            f"p99 {plain['latency_ms_p99']:.3f} ms")
+        del srcs64
+        torch.cuda.empty_cache()
+        results[name] = {"sizes": list(szs), "weights": list(wts), "requests": count,
+                         "sources": "each request's own 8 Gaussian blobs (seed 4 trace)",
+                         "saturation": sat, "poisson_rate_hz": rate, "poisson": op,
+                         "small_budget": small, "plain_fp64_same_arrivals": plain,
+                         "accuracy_first_of_each_size": acc, "budget_bytes": budget,
+                         "max_inflight": max_inflight}
     return results
