@@ -203,6 +203,27 @@ pspfft_status pspfft_destroy(pspfft_plan_t plan);
  */
 pspfft_status pspfft_solve(pspfft_plan_t plan, const void *S, void *Phi, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid allocation): as
+ * pspfft_solve, with the workspace in a library-owned device array of
+ * PSPFFT_NOALLOC_MAX_BYTES (128 MiB) instead of the plan's default workspace.
+ * The call allocates no device memory and creates no HIP objects; the caller
+ * creates the plan beforehand and passes S and Phi as for pspfft_solve.  Every
+ * GPU the library runs on holds one such array from the time the library's
+ * device code is loaded there until the process ends; the array of the current
+ * device (which must be the plan's) is used.  Meshes whose workspace
+ * (pspfft_workspace_bytes) exceeds PSPFFT_NOALLOC_MAX_BYTES return
+ * PSPFFT_ERR_UNSUPPORTED_SIZE with an error message (FP32 192^3 and FP64 160^3
+ * fit, FP32 256^3 does not).  Nothing in the array has to start at zero (every pass writes
+ * what the next one reads).  All calls on one GPU share its array: calls that
+ * overlap in time on that GPU (different streams, or different host threads
+ * without ordering) race and give wrong results.  pspfft_destroy does not wait
+ * for these solves: synchronise their stream before destroying the plan.
+ */
+#define PSPFFT_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+pspfft_status pspfft_solve_noalloc(pspfft_plan_t plan, const void *S, void *Phi, hipStream_t stream);
+
 /* Allocate a workspace for one in-flight solve of this plan
  * (pspfft_workspace_bytes bytes of device memory, owned by the workspace). */
 pspfft_status pspfft_workspace_create(pspfft_plan_t plan, pspfft_workspace_t *out);

@@ -40,7 +40,9 @@ EXPORTS = (
     "pspfft_plan_bytes", "pspfft_plan_resident_bytes", "pspfft_workspace_bytes", "pspfft_pass_bytes",
     "pspfft_plan_info", "pspfft_plan_green", "pspfft_status_string",
     "pspfft_set_verbosity", "pspfft_get_verbosity", "pspfft_set_log_callback",
+    "pspfft_solve_noalloc",
 )
+NOALLOC_MAX_BYTES = 128 << 20  # PSPFFT_NOALLOC_MAX_BYTES
 
 # pspfft_verbosity (Sec. 3.2, VerbosityOption)
 CONSOLE_ERROR, CONSOLE_WARNING, CONSOLE_INFO_1, CONSOLE_INFO_2 = range(4)
@@ -85,6 +87,7 @@ def load():
         "pspfft_workspace_ztile": ([vp], ip),
         "pspfft_destroy": ([vp], ip),
         "pspfft_solve": ([vp, vp, vp, vp], ip),
+        "pspfft_solve_noalloc": ([vp, vp, vp, vp], ip),
         "pspfft_workspace_create": ([vp, vpp], ip),
         "pspfft_workspace_wrap": ([vp, vp, sz, vpp], ip),
         "pspfft_workspace_destroy": ([vp], ip),

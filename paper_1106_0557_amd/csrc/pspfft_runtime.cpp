@@ -1121,3 +1121,27 @@ pspfft_status pspfft_plan_green(pspfft_plan_t plan, void *dst, hipStream_t strea
 }
 
 }  // extern "C"
+
+namespace pspfft {
+// Report a failure about `plan` at level error (for entry points defined in
+// other files) and return its status.
+pspfft_status report_failure(pspfft_status st, pspfft_plan_t plan, const char *what) {
+    return fail(st, plan ? plan->verbosity : -1, "%s", what);
+}
+
+// One solve with `bytes` bytes of device memory at `mem` (256-byte aligned) as
+// its workspace, through a workspace handle on the stack: allocates nothing.
+pspfft_status solve_on(pspfft_plan_t plan, void *mem, size_t bytes, const void *S, void *Phi, hipStream_t stream) {
+    if (!plan || !mem || !S || !Phi) return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan ? plan->verbosity : -1, "solve: null argument");
+    if (bytes < ws_bytes(plan->n, plan->prec) || reinterpret_cast<uintptr_t>(mem) % 256 != 0)
+        return fail(PSPFFT_ERR_INVALID_ARGUMENT, plan->verbosity, "solve: workspace memory too small or misaligned");
+    pspfft_workspace_s w;  // a handle on the stack: no allocation
+    w.plan = plan;
+    w.owned = false;
+    w.mem = mem;
+    w.bytes = bytes;
+    ws_split(&w, plan->n, plan->prec);
+    pspfft_workspace_t wp = &w;
+    return solve_all(1, &plan, &wp, &S, &Phi, stream, false);
+}
+}  // namespace pspfft
