@@ -186,10 +186,12 @@ int pspfft_plan_spectrum_kz_fastest(pspfft_plan_t plan);
  */
 int pspfft_workspace_ztile(pspfft_plan_t plan);
 
-/* Release a plan and everything it owns (Sec. 3.2, Destroy).  Waits for the
- * kernels already launched for this plan (its last launch on each stream it
- * ran on), not for other work on the device.  Workspaces created for the plan
- * must be destroyed first.  NULL returns PSPFFT_ERR_INVALID_ARGUMENT. */
+/* Release a plan and everything it owns (Sec. 3.2, Destroy).  The memory is
+ * freed with hipFree, which waits for the work already queued on the device,
+ * so kernels still reading the plan finish first; destroying a plan therefore
+ * waits for every stream of the device: destroy plans when the device is idle
+ * (a server's plan cache at shutdown).  Workspaces created for the plan must be
+ * destroyed first.  NULL returns PSPFFT_ERR_INVALID_ARGUMENT. */
 pspfft_status pspfft_destroy(pspfft_plan_t plan);
 
 /*
@@ -218,8 +220,7 @@ pspfft_status pspfft_solve(pspfft_plan_t plan, const void *S, void *Phi, hipStre
  * fit, FP32 256^3 does not).  Nothing in the array has to start at zero (every pass writes
  * what the next one reads).  All calls on one GPU share its array: calls that
  * overlap in time on that GPU (different streams, or different host threads
- * without ordering) race and give wrong results.  pspfft_destroy does not wait
- * for these solves: synchronise their stream before destroying the plan.
+ * without ordering) race and give wrong results.
  */
 #define PSPFFT_NOALLOC_MAX_BYTES ((size_t)128 << 20)
 pspfft_status pspfft_solve_noalloc(pspfft_plan_t plan, const void *S, void *Phi, hipStream_t stream);
@@ -233,8 +234,8 @@ pspfft_status pspfft_workspace_create(pspfft_plan_t plan, pspfft_workspace_t *ou
 pspfft_status pspfft_workspace_wrap(pspfft_plan_t plan, void *memory, size_t bytes,
                                     pspfft_workspace_t *out);
 
-/* Release a workspace handle, and its memory unless it was wrapped (after the
- * kernels launched so far for its plan have finished). */
+/* Release a workspace handle, and its memory unless it was wrapped (hipFree,
+ * after the work queued on the device). */
 pspfft_status pspfft_workspace_destroy(pspfft_workspace_t ws);
 
 /* As pspfft_solve, with an explicit workspace created for the same plan. */

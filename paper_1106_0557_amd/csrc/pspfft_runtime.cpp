@@ -43,9 +43,7 @@ struct pspfft_plan_s {
     bool fused = false;      // x and y transforms of a z plane in one kernel
     int pE = 0, pK = 0;      // radix family and last radix of those kernels
     int verbosity = -1;      // the plan's own message level (Sec. 3.2, VerbosityOption); -1: the process's
-    std::mutex mu;           // guards ws creation and `uses`
-    // the plan's last launch on each stream it ran on: what destroy waits for
-    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+    std::mutex mu;           // guards the creation of the default workspace
 };
 
 struct pspfft_workspace_s {
@@ -342,33 +340,12 @@ void ws_split(pspfft_workspace_t w, const int n[3], pspfft_precision prec) {
     w->Wn = static_cast<char *>(w->mem) + round_up(main, 256);
 }
 
-// Wait until every launch issued for plan p so far has finished (its last
-// launch on each stream it ran on), without waiting for other work.
-void wait_uses(pspfft_plan_t p) {
-    std::lock_guard<std::mutex> lk(p->mu);
-    for (auto &u : p->uses) (void)hipEventSynchronize(u.second);
-}
-
-// Note that plan p has just been launched on `stream`.
-pspfft_status record_use(pspfft_plan_t p, hipStream_t stream) {
-    std::lock_guard<std::mutex> lk(p->mu);
-    for (auto &u : p->uses)
-        if (u.first == stream) return hipEventRecord(u.second, stream) == hipSuccess ? PSPFFT_OK : PSPFFT_ERR_DEVICE;
-    if (p->uses.size() >= 64) {  // many short-lived streams: keep the list short
-        (void)hipEventSynchronize(p->uses.front().second);
-        (void)hipEventDestroy(p->uses.front().second);
-        p->uses.erase(p->uses.begin());
-    }
-    hipEvent_t ev = nullptr;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return PSPFFT_ERR_DEVICE;
-    p->uses.emplace_back(stream, ev);
-    return hipEventRecord(ev, stream) == hipSuccess ? PSPFFT_OK : PSPFFT_ERR_DEVICE;
-}
-
+// Frees with hipFree, which in the HIP runtime waits for all work queued on the
+// device first (measured: a hipFree issued while another stream runs returns
+// when that stream's work is done), so a plan's memory is never released under
+// a kernel that still reads it.
 void destroy_plan(pspfft_plan_t p) {
     if (!p) return;
-    for (auto &u : p->uses) (void)hipEventDestroy(u.second);
-    p->uses.clear();
     if (p->ws) {
         if (p->ws->owned && p->ws->mem) (void)hipFree(p->ws->mem);
         delete p->ws;
@@ -677,10 +654,8 @@ pspfft_status launch_planes(bool fwd, const std::vector<int> &all, const pspfft_
 
 // One pass for `count` problems.  Plans with fused planes run their x and y
 // transforms together in X_FWD and X_INV and have nothing to do in Y_FWD and Y_INV.
-// track: note the launch stream per plan (what pspfft_destroy waits for); the
-// allocation-free solve creates no events and does not.
 pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
-                       const void *const *S, void *const *Phi, hipStream_t stream, bool track = true) {
+                       const void *const *S, void *const *Phi, hipStream_t stream) {
     const pspfft_status bad = PSPFFT_ERR_INVALID_ARGUMENT;
     if (count < 0) return fail(bad, -1, "pass %d: negative count", mode);
     if (count == 0) return PSPFFT_OK;
@@ -707,18 +682,12 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
     if (!planes.empty()) st = launch_planes(mode == pspfft::X_FWD, planes, plans, ws, S, Phi, stream);
     if (st == PSPFFT_OK && !lines.empty()) st = launch_lines(mode, lines, plans, ws, S, Phi, stream);
     if (st != PSPFFT_OK) return fail(st, plans[0]->verbosity, "pass %d of %d problems", mode, count);
-    // what destroying a plan (or one of its workspaces) must wait for
-    for (int i = 0; track && i < count && st == PSPFFT_OK; ++i) {
-        bool seen = false;
-        for (int j = 0; j < i && !seen; ++j) seen = plans[j] == plans[i];
-        if (!seen) st = record_use(plans[i], stream);
-    }
-    return st;
+    return PSPFFT_OK;
 }
 
 
 pspfft_status solve_all(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws, const void *const *S,
-                        void *const *Phi, hipStream_t stream, bool track);
+                        void *const *Phi, hipStream_t stream);
 
 }  // namespace
 
@@ -914,8 +883,6 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
 
 pspfft_status pspfft_destroy(pspfft_plan_t plan) {
     if (!plan) return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_destroy: null plan");
-    // wait for this plan's own launches only, not for the whole device
-    wait_uses(plan);
     PSPFFT_MSG(plan->verbosity, PSPFFT_CONSOLE_INFO_1, "destroying plan %d x %d x %d %s", plan->n[0], plan->n[1],
                plan->n[2], plan->prec == PSPFFT_FP32 ? "fp32" : "fp64");
     destroy_plan(plan);
@@ -962,10 +929,7 @@ pspfft_status pspfft_workspace_destroy(pspfft_workspace_t ws) {
     if (ws->plan && ws == ws->plan->ws)
         return fail(PSPFFT_ERR_INVALID_ARGUMENT, ws->plan->verbosity,
                     "pspfft_workspace_destroy: the plan's default workspace goes with the plan");
-    if (ws->owned && ws->mem) {
-        wait_uses(ws->plan);  // launches of its plan, the only ones that can use it
-        (void)hipFree(ws->mem);
-    }
+    if (ws->owned && ws->mem) (void)hipFree(ws->mem);  // after the work queued on the device
     delete ws;
     return PSPFFT_OK;
 }
@@ -980,14 +944,14 @@ pspfft_status pspfft_pass_batched(pspfft_pass pass, int count, const pspfft_plan
 
 pspfft_status pspfft_solve_batched(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
                                    const void *const *S, void *const *Phi, hipStream_t stream) {
-    return solve_all(count, plans, ws, S, Phi, stream, true);
+    return solve_all(count, plans, ws, S, Phi, stream);
 }
 
 }  // extern "C"
 
 namespace {
 pspfft_status solve_all(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws, const void *const *S,
-                        void *const *Phi, hipStream_t stream, bool track) {
+                        void *const *Phi, hipStream_t stream) {
     if (count < 0 || (count > 0 && (!plans || !ws || !S || !Phi)))
         return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_solve_batched: count %d or null array", count);
     for (int i = 0; i < count; ++i)
@@ -995,7 +959,7 @@ pspfft_status solve_all(int count, const pspfft_plan_t *plans, const pspfft_work
             if (ws[i] == ws[j])
                 return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_solve_batched: problems %d and %d share a workspace", i, j);
     for (int mode = pspfft::X_FWD; mode <= pspfft::X_INV; ++mode) {
-        pspfft_status st = run_pass(mode, count, plans, ws, S, Phi, stream, track);
+        pspfft_status st = run_pass(mode, count, plans, ws, S, Phi, stream);
         if (st != PSPFFT_OK) return st;
     }
     return PSPFFT_OK;
@@ -1142,6 +1106,6 @@ pspfft_status solve_on(pspfft_plan_t plan, void *mem, size_t bytes, const void *
     w.bytes = bytes;
     ws_split(&w, plan->n, plan->prec);
     pspfft_workspace_t wp = &w;
-    return solve_all(1, &plan, &wp, &S, &Phi, stream, false);
+    return solve_all(1, &plan, &wp, &S, &Phi, stream);
 }
 }  // namespace pspfft
