@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--batch", type=int, default=16, help="FP32 solves per served step")
+    ap.add_argument("--batch", type=int, default=32, help="FP32 solves per served step")
     ap.add_argument("--fp64-solves", type=int, default=2500, help="sequential FP64 plain solves (paper: 2500)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
