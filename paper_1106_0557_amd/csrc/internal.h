@@ -90,7 +90,9 @@ struct LaunchArgs {
     int nwg;          // workgroups doing work (the grid may be padded to a multiple of 8)
     int xcd_remap;    // renumber workgroups so each XCD gets a contiguous range
     int wave_z;       // z pass: spectra kz-fastest, lines kept within one wavefront
-    int gtile;        // generic line kernel: lines per workgroup
+    int gtile;        // generic line kernel: lines per workgroup (a power of two)
+    int glmax;        // generic line kernel: longest line of the launch
+    int gtw;          // generic line kernel: stage twiddles copied into LDS after the two buffers
     Segment seg[kMaxProblems];
     ProbArg p[kMaxProblems];
 };
@@ -266,7 +268,7 @@ inline hipError_t launch_plane(bool fwd, int prec, int E, int K, const LaunchArg
 
 // Generic line kernel (any 2^a 3^b 5^c length): `grid` workgroups of 256
 // threads, each owning args.gtile lines, with `lds` bytes of LDS (two buffers of
-// gtile * (L + 1) complex values for the longest line of the launch).
+// gtile * (glmax + 1) complex values, then, with args.gtw, the stage twiddles).
 hipError_t launch_generic(int mode, int prec, const LaunchArgs &args, int grid, size_t lds, hipStream_t stream);
 
 // Green's-function spectrum in FP64: fills the octant (nz+1)(ny+1)(nx+1) of G

@@ -5,16 +5,19 @@
 // unnormalised transforms as the family kernels (Sec. 2.1 mesh doubling, Sec.
 // 2.2.2 sequence of 1D transforms), so one plan may mix family and generic axes.
 //
-// A workgroup of 256 threads owns `tile` whole lines.  The lines are loaded into
-// one of two LDS buffers; every stage (radix R in {2, 3, 4, 5, 8, 9}, Stockham
-// autosort, decimation in time) reads one buffer and writes the other:
+// A workgroup of 256 threads owns `tile` whole lines (a power of two); each
+// line gets 256 / tile threads, which walk its positions j0, j0 + tpl, ...  The
+// lines are loaded into one of two LDS buffers; every stage (radices up to 27,
+// Stockham autosort, decimation in time) reads one buffer and writes the other:
 //   for each butterfly j < L/R of a line, k = j mod Ns:
 //     x_r = in[j + r L/R] * exp(DIR 2 pi i r k / (Ns R)),  r < R
 //     out[(j - k) R + k + r Ns] = DFT_R(x)[r]
 // with Ns the product of the earlier radices; the result is in natural order.
 // Column passes (y, z) keep element (line c, position p) at p*tile + c, so a
 // wavefront's global accesses cover `tile` adjacent kx and its LDS accesses are
-// consecutive; row passes (x) keep it at c*(L+1) + p.
+// consecutive; row passes (x) keep it at c*(L+1) + p.  Index arithmetic is
+// shifts and adds: a thread's line is fixed, its positions advance by tpl, and
+// k = j mod Ns advances by tpl mod Ns.
 #include "fft_core.h"
 #include "internal.h"
 
@@ -22,58 +25,82 @@ namespace pspfft {
 namespace {
 
 constexpr int kGenBlock = 256;
+constexpr int kGenShift = 8;  // log2(kGenBlock)
 
 template <bool ROW>
 __device__ __forceinline__ int gidx(int c, int p, int tile, int L) {
     return ROW ? c * (L + 1) + p : p * tile + c;
 }
 
-// One stage of radix R over every line of the tile: src -> dst.
+// This thread's line of the tile and its first position; tpl threads per line.
+struct GenMap {
+    int c, j0, tpl;
+};
+template <bool ROW>
+__device__ __forceinline__ GenMap gen_map(int tshift) {
+    const int tid = static_cast<int>(threadIdx.x);
+    GenMap m;
+    m.tpl = kGenBlock >> tshift;
+    if constexpr (ROW) {  // rows: consecutive lanes along a line
+        m.c = tid >> (kGenShift - tshift);
+        m.j0 = tid & (m.tpl - 1);
+    } else {              // columns: consecutive lanes on adjacent lines
+        m.c = tid & ((1 << tshift) - 1);
+        m.j0 = tid >> tshift;
+    }
+    return m;
+}
+
+// One stage of radix R over the thread's butterflies of its line: src -> dst.
 template <typename T, int R, int DIR, bool ROW>
-__device__ void gen_stage(const cx<T> *src, cx<T> *dst, int tile, int L, int Ns, const cx<T> *tw) {
+__device__ void gen_stage(const cx<T> *src, cx<T> *dst, const GenMap &m, int tile, int L, int Ns,
+                          const cx<T> *tw) {
     const int nb = L / R;  // butterflies per line
-    const int total = tile * nb;
-    for (int w = threadIdx.x; w < total; w += kGenBlock) {
-        int c, j;
-        if constexpr (ROW) {
-            c = w / nb;
-            j = w - c * nb;
-        } else {
-            j = w / tile;
-            c = w - j * tile;
-        }
-        const int k = j % Ns;
+    int k = m.j0 % Ns;
+    const int step = m.tpl % Ns;
+    for (int j = m.j0; j < nb; j += m.tpl) {
         cx<T> x[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = src[gidx<ROW>(c, j + r * nb, tile, L)];
+        for (int r = 0; r < R; ++r) x[r] = src[gidx<ROW>(m.c, j + r * nb, tile, L)];
         if (Ns > 1) {
-            const cx<T> *t = tw + static_cast<size_t>(k) * (R - 1);
+            const cx<T> *t = tw + k * (R - 1);
 #pragma unroll
             for (int r = 1; r < R; ++r) x[r] = DIR > 0 ? cmulc(x[r], t[r - 1]) : cmul(x[r], t[r - 1]);
         }
         dft<R, DIR>(x);
         const int base = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[gidx<ROW>(c, base + r * Ns, tile, L)] = x[r];
+        for (int r = 0; r < R; ++r) dst[gidx<ROW>(m.c, base + r * Ns, tile, L)] = x[r];
+        k += step;
+        if (k >= Ns) k -= Ns;
     }
 }
 
 // Transform every line of the tile held in `a` (the other buffer `b` is
-// scratch).  Returns the buffer that holds the result.  Opens with a barrier, so
-// the caller's writes to `a` are visible, and ends with one.
+// scratch; `tw` the stage twiddle table, in LDS or global memory).  Returns the
+// buffer that holds the result.  Opens with a barrier, so the caller's writes
+// to `a` are visible, and ends with one.
 template <typename T, int DIR, bool ROW>
-__device__ cx<T> *gen_transform(cx<T> *a, cx<T> *b, int tile, const AxisPlan &ax) {
-    const cx<T> *tw = static_cast<const cx<T> *>(ax.tw);
+__device__ cx<T> *gen_transform(cx<T> *a, cx<T> *b, const GenMap &m, int tile, const AxisPlan &ax,
+                                const cx<T> *tw) {
     for (int s = 0; s < ax.nst; ++s) {
         __syncthreads();
         const cx<T> *t = tw + ax.twoff[s];
+        const int L = ax.L, Ns = ax.Ns[s];
         switch (ax.R[s]) {
-            case 2: gen_stage<T, 2, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
-            case 3: gen_stage<T, 3, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
-            case 4: gen_stage<T, 4, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
-            case 5: gen_stage<T, 5, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
-            case 8: gen_stage<T, 8, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
-            case 9: gen_stage<T, 9, DIR, ROW>(a, b, tile, ax.L, ax.Ns[s], t); break;
+            case 2: gen_stage<T, 2, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 3: gen_stage<T, 3, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 4: gen_stage<T, 4, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 5: gen_stage<T, 5, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 6: gen_stage<T, 6, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 8: gen_stage<T, 8, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 9: gen_stage<T, 9, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 10: gen_stage<T, 10, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 12: gen_stage<T, 12, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 15: gen_stage<T, 15, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 16: gen_stage<T, 16, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 25: gen_stage<T, 25, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
+            case 27: gen_stage<T, 27, DIR, ROW>(a, b, m, tile, L, Ns, t); break;
             default: break;  // the host builds only these radices
         }
         cx<T> *tmp = a;
@@ -119,81 +146,83 @@ __global__ void __launch_bounds__(kGenBlock) generic_kernel(const LaunchArgs arg
     const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
     const int L = ax.L;
     const int tile = args.gtile;
+    const int tshift = __builtin_ctz(static_cast<unsigned>(tile));
     cx<T> *A = reinterpret_cast<cx<T> *>(smem);
     cx<T> *B = A + static_cast<size_t>(tile) * (L + 1);
+    // stage twiddles: in LDS after the two buffers of the launch's longest line
+    // when the host found room (args.gtw), else read from the plan's table
+    const cx<T> *tw = static_cast<const cx<T> *>(ax.tw);
+    if (args.gtw) {
+        cx<T> *twl = A + static_cast<size_t>(2) * tile * (args.glmax + 1);
+        for (int i = static_cast<int>(threadIdx.x); i < ax.ntw; i += kGenBlock) twl[i] = tw[i];
+        tw = twl;  // published by the first stage's barrier
+    }
     cx<T> *W = static_cast<cx<T> *>(pa.W);
     cx<T> *Wn = static_cast<cx<T> *>(pa.Wn);
     const bool nyq = local >= sg.wg_main;
     if (nyq) local -= sg.wg_main;
-    const long g0 = static_cast<long>(local) * tile;
-    const int tid = threadIdx.x;
+    const GenMap m = gen_map<ROW>(tshift);
+    const long g = static_cast<long>(local) * tile + m.c;  // this thread's line
     const cx<T> zero = {T(0), T(0)};
 
     if constexpr (MODE == X_FWD) {
         // rows r = z*ny + y of S, zero-padded to 2nx, packed u[j] = s[2j] + i s[2j+1] (L = nx)
-        const long nrows = static_cast<long>(ny) * nz;
-        const T *S = static_cast<const T *>(pa.S);
-        for (int w = tid; w < tile * L; w += kGenBlock) {
-            const int c = w / L, j = w - c * L;
-            const long g = g0 + c;
+        const bool active = g < static_cast<long>(ny) * nz;
+        const T *row = static_cast<const T *>(pa.S) + static_cast<size_t>(active ? g : 0) * nx;
+        for (int j = m.j0; j < L; j += m.tpl) {
             cx<T> v = zero;
-            if (g < nrows) {
-                const T *row = S + static_cast<size_t>(g) * nx;
+            if (active) {
                 if (2 * j < nx) v.x = row[2 * j];
                 if (2 * j + 1 < nx) v.y = row[2 * j + 1];
             }
-            A[gidx<true>(c, j, tile, L)] = v;
+            A[gidx<true>(m.c, j, tile, L)] = v;
         }
-        const cx<T> *U = gen_transform<T, -1, true>(A, B, tile, ax);
-        // split step: X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k]), k <= n
-        const cx<T> *post = static_cast<const cx<T> *>(ax.post);
-        for (int w = tid; w < tile * (L + 1); w += kGenBlock) {
-            const int c = w / (L + 1), k = w - c * (L + 1);
-            const long g = g0 + c;
-            if (g >= nrows) continue;
-            const cx<T> u = U[gidx<true>(c, k == L ? 0 : k, tile, L)];
-            const cx<T> m = U[gidx<true>(c, k == 0 ? 0 : L - k, tile, L)];
-            const cx<T> a = {static_cast<T>(0.5) * (u.x + m.x), static_cast<T>(0.5) * (u.y - m.y)};
-            const cx<T> b = {static_cast<T>(0.5) * (u.x - m.x), static_cast<T>(0.5) * (u.y + m.y)};
-            const cx<T> e = k < L ? post[k] : cx<T>{T(-1), T(0)};
-            const cx<T> eb = cmul(e, b);
-            const cx<T> X = {a.x + eb.y, a.y - eb.x};  // a - i e b
+        const cx<T> *U = gen_transform<T, -1, true>(A, B, m, tile, ax, tw);
+        if (active) {
+            // split step: X[k] = (U[k] + U*[n-k])/2 - (i/2) exp(-i pi k/n) (U[k] - U*[n-k]), k <= n
+            const cx<T> *post = static_cast<const cx<T> *>(ax.post);
             const int z = static_cast<int>(g / ny), y = static_cast<int>(g - static_cast<long>(z) * ny);
-            if (k < nx) W[w_row(z, y, ny, nx, pl.zb) + k] = X;
-            else Wn[static_cast<size_t>(z) * 2 * ny + y] = X;
+            cx<T> *wrow = W + w_row(z, y, ny, nx, pl.zb);
+            for (int k = m.j0; k <= L; k += m.tpl) {
+                const cx<T> u = U[gidx<true>(m.c, k == L ? 0 : k, tile, L)];
+                const cx<T> w = U[gidx<true>(m.c, k == 0 ? 0 : L - k, tile, L)];
+                const cx<T> a = {static_cast<T>(0.5) * (u.x + w.x), static_cast<T>(0.5) * (u.y - w.y)};
+                const cx<T> b = {static_cast<T>(0.5) * (u.x - w.x), static_cast<T>(0.5) * (u.y + w.y)};
+                const cx<T> e = k < L ? post[k] : cx<T>{T(-1), T(0)};
+                const cx<T> eb = cmul(e, b);
+                const cx<T> X = {a.x + eb.y, a.y - eb.x};  // a - i e b
+                if (k < nx) wrow[k] = X;
+                else Wn[static_cast<size_t>(z) * 2 * ny + y] = X;
+            }
         }
     } else if constexpr (MODE == X_INV) {
         // X[k], k <= n, of rows y < ny; Hermitian extension through the inverse split step
-        const long nrows = static_cast<long>(ny) * nz;
-        for (int w = tid; w < tile * (L + 1); w += kGenBlock) {
-            const int c = w / (L + 1), k = w - c * (L + 1);
-            const long g = g0 + c;
+        const bool active = g < static_cast<long>(ny) * nz;
+        const int z = active ? static_cast<int>(g / ny) : 0;
+        const int y = active ? static_cast<int>(g - static_cast<long>(z) * ny) : 0;
+        const cx<T> *wrow = W + w_row(z, y, ny, nx, pl.zb);
+        for (int k = m.j0; k <= L; k += m.tpl) {
             cx<T> v = zero;
-            if (g < nrows) {
-                const int z = static_cast<int>(g / ny), y = static_cast<int>(g - static_cast<long>(z) * ny);
-                v = k < nx ? W[w_row(z, y, ny, nx, pl.zb) + k] : Wn[static_cast<size_t>(z) * 2 * ny + y];
-            }
-            B[gidx<true>(c, k, tile, L)] = v;  // L + 1 slots per row
+            if (active) v = k < nx ? wrow[k] : Wn[static_cast<size_t>(z) * 2 * ny + y];
+            B[gidx<true>(m.c, k, tile, L)] = v;  // L + 1 slots per row
         }
         __syncthreads();
         // U[k] = (X[k] + X*[n-k]) + i exp(+i pi k/n) (X[k] - X*[n-k]), k < n
         const cx<T> *post = static_cast<const cx<T> *>(ax.post);
-        for (int w = tid; w < tile * L; w += kGenBlock) {
-            const int c = w / L, k = w - c * L;
-            const cx<T> xk = B[gidx<true>(c, k, tile, L)];
-            const cx<T> xm = B[gidx<true>(c, L - k, tile, L)];
+        for (int k = m.j0; k < L; k += m.tpl) {
+            const cx<T> xk = B[gidx<true>(m.c, k, tile, L)];
+            const cx<T> xm = B[gidx<true>(m.c, L - k, tile, L)];
             const cx<T> e = {xk.x + xm.x, xk.y - xm.y};
             const cx<T> o = cmulc(cx<T>{xk.x - xm.x, xk.y + xm.y}, post[k]);  // times exp(+i pi k/n)
-            A[gidx<true>(c, k, tile, L)] = cx<T>{e.x - o.y, e.y + o.x};     // e + i o
+            A[gidx<true>(m.c, k, tile, L)] = cx<T>{e.x - o.y, e.y + o.x};   // e + i o
         }
-        const cx<T> *u = gen_transform<T, +1, true>(A, B, tile, ax);
-        T *Phi = static_cast<T *>(pa.Phi);
-        for (int w = tid; w < tile * nx; w += kGenBlock) {
-            const int c = w / nx, x = w - c * nx;
-            const long g = g0 + c;
-            if (g >= nrows) continue;
-            const cx<T> v = u[gidx<true>(c, x >> 1, tile, L)];
-            Phi[static_cast<size_t>(g) * nx + x] = (x & 1) ? v.y : v.x;
+        const cx<T> *u = gen_transform<T, +1, true>(A, B, m, tile, ax, tw);
+        if (active) {
+            T *Phi = static_cast<T *>(pa.Phi) + static_cast<size_t>(g) * nx;
+            for (int x = m.j0; x < nx; x += m.tpl) {
+                const cx<T> v = u[gidx<true>(m.c, x >> 1, tile, L)];
+                Phi[x] = (x & 1) ? v.y : v.x;
+            }
         }
     } else {
         // column lines: y passes over (z, kx), z pass over (ky, kx); Nyquist lines kx = nx
@@ -208,44 +237,36 @@ __global__ void __launch_bounds__(kGenBlock) generic_kernel(const LaunchArgs arg
             nin = MODE == Y_FWD ? ny : L;
             nout = MODE == Y_FWD ? L : ny;
         }
-        for (int w = tid; w < tile * L; w += kGenBlock) {
-            const int p = w / tile, c = w - p * tile;
-            const long g = g0 + c;
+        const bool active = g < nlines;
+        for (int p = m.j0; p < L; p += m.tpl) {
             cx<T> v = zero;
-            if (g < nlines && p < nin) v = *col_elem<T, MODE>(pl, W, Wn, nyq, g, p);
-            A[gidx<false>(c, p, tile, L)] = v;
+            if (active && p < nin) v = *col_elem<T, MODE>(pl, W, Wn, nyq, g, p);
+            A[gidx<false>(m.c, p, tile, L)] = v;
         }
         cx<T> *res;
         if constexpr (MODE == Z_CONV) {
-            res = gen_transform<T, -1, false>(A, B, tile, ax);
+            res = gen_transform<T, -1, false>(A, B, m, tile, ax, tw);
             // multiply by the spectrum, even in ky and kz: octant index min(k, 2n - k)
-            const T *G = static_cast<const T *>(pl.G);
-            const T *Gn = static_cast<const T *>(pl.Gn);
-            for (int w = tid; w < tile * L; w += kGenBlock) {
-                const int kz = w / tile, c = w - kz * tile;
-                const long g = g0 + c;
-                if (g >= nlines) continue;
-                const int kzo = kz <= nz ? kz : L - kz;
-                T gv;
-                if (nyq) {
-                    const int ky = static_cast<int>(g), kyo = ky <= ny ? ky : 2 * ny - ky;
-                    gv = Gn[static_cast<size_t>(kzo) * (ny + 1) + kyo];
-                } else {
-                    const int ky = static_cast<int>(g / nx), kx = static_cast<int>(g - static_cast<long>(ky) * nx);
-                    const int kyo = ky <= ny ? ky : 2 * ny - ky;
-                    gv = G[(static_cast<size_t>(kzo) * (ny + 1) + kyo) * nx + kx];
+            if (active) {
+                const T *G = static_cast<const T *>(pl.G);
+                const T *Gn = static_cast<const T *>(pl.Gn);
+                const int ky = nyq ? static_cast<int>(g) : static_cast<int>(g / nx);
+                const int kx = nyq ? nx : static_cast<int>(g - static_cast<long>(ky) * nx);
+                const int kyo = ky <= ny ? ky : 2 * ny - ky;
+                for (int kz = m.j0; kz < L; kz += m.tpl) {
+                    const int kzo = kz <= nz ? kz : L - kz;
+                    const T gv = nyq ? Gn[static_cast<size_t>(kzo) * (ny + 1) + kyo]
+                                     : G[(static_cast<size_t>(kzo) * (ny + 1) + kyo) * nx + kx];
+                    cx<T> &e = res[gidx<false>(m.c, kz, tile, L)];
+                    e = cx<T>{e.x * gv, e.y * gv};
                 }
-                cx<T> &e = res[gidx<false>(c, kz, tile, L)];
-                e = cx<T>{e.x * gv, e.y * gv};
             }
-            res = gen_transform<T, +1, false>(res, res == A ? B : A, tile, ax);
+            res = gen_transform<T, +1, false>(res, res == A ? B : A, m, tile, ax, tw);
         } else {
-            res = gen_transform<T, MODE == Y_FWD ? -1 : +1, false>(A, B, tile, ax);
+            res = gen_transform<T, MODE == Y_FWD ? -1 : +1, false>(A, B, m, tile, ax, tw);
         }
-        for (int w = tid; w < tile * nout; w += kGenBlock) {
-            const int p = w / tile, c = w - p * tile;
-            const long g = g0 + c;
-            if (g < nlines) *col_elem<T, MODE>(pl, W, Wn, nyq, g, p) = res[gidx<false>(c, p, tile, L)];
+        if (active) {
+            for (int p = m.j0; p < nout; p += m.tpl) *col_elem<T, MODE>(pl, W, Wn, nyq, g, p) = res[gidx<false>(m.c, p, tile, L)];
         }
     }
 }

@@ -225,20 +225,23 @@ void turn(long j, long M, double &c, double &s) {
 }
 
 // Radices of the generic line kernel for a length L = 2^a 3^b 5^c, in stage
-// order: 8s, then one 4 or 2, then 5s, 9s and a last 3.
+// order: the largest of its radices that divides what is left, each time
+// (few stages: every stage is a round trip through LDS).
 std::vector<int> generic_radices(int L) {
+    static const int kRadices[] = {27, 25, 16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
     std::vector<int> r;
-    int m = L, p2 = 0;
-    while (m % 2 == 0) {
-        m /= 2;
-        ++p2;
+    int m = L;
+    while (m > 1) {
+        int pick = 0;
+        for (int R : kRadices)
+            if (m % R == 0) {
+                pick = R;
+                break;
+            }
+        if (!pick) return {};  // not 2^a 3^b 5^c
+        r.push_back(pick);
+        m /= pick;
     }
-    for (; p2 >= 3; p2 -= 3) r.push_back(8);
-    if (p2 == 2) r.push_back(4);
-    if (p2 == 1) r.push_back(2);
-    for (; m % 5 == 0; m /= 5) r.push_back(5);
-    for (; m % 9 == 0; m /= 9) r.push_back(9);
-    for (; m % 3 == 0; m /= 3) r.push_back(3);
     return r;
 }
 
@@ -255,6 +258,7 @@ bool build_axis(int axis, int n, pspfft_precision prec, AxisPlan &ax, std::vecto
     ax.E = E;
     ax.NB = E ? L / E : 0;
     const std::vector<int> gen = E ? std::vector<int>() : generic_radices(L);
+    if (!E && static_cast<int>(gen.size()) > pspfft::kMaxStages) return false;
     int rem = L, Ns = 1, s = 0;
     tw.clear();
     while (rem > 1) {
@@ -397,7 +401,8 @@ void pass_lines(int mode, const int n[3], long &main, long &nyq) {
 
 // Lines per workgroup of the generic kernel for lines of up to L points: the
 // largest power of two up to 64 whose two LDS buffers fit 160 KB, with at most
-// max(L, 4096) points per workgroup (about 16 per thread).
+// max(L, 4096) points per workgroup (about 16 per thread).  Its stage twiddles
+// go into LDS too where they fit beside the buffers.
 int generic_tile(int L, size_t csz) {
     int t = 64;
     while (t > 1 && (static_cast<size_t>(2) * t * (L + 1) * csz > 160 * 1024 ||
@@ -447,6 +452,11 @@ pspfft_status launch_generic_lines(int mode, const std::vector<int> &all, const 
                 sg.group = 1;
             }
             args.gtile = generic_tile(lmax, csz);
+            args.glmax = lmax;
+            int ntw = 0;
+            for (size_t j = c0; j < c1; ++j) ntw = std::max(ntw, plans[idx[j]]->host.ax[axis].ntw);
+            const size_t bufs = static_cast<size_t>(2) * args.gtile * (lmax + 1) * csz;
+            args.gtw = bufs + ntw * csz <= 160 * 1024 ? 1 : 0;
             long wg = 0;
             for (int k = 0; k < args.nseg; ++k) {
                 pspfft::Segment &sg = args.seg[k];
@@ -460,7 +470,7 @@ pspfft_status launch_generic_lines(int mode, const std::vector<int> &all, const 
             }
             if (wg > 0x7fffffffL) return PSPFFT_ERR_UNSUPPORTED_SIZE;
             args.nwg = static_cast<int>(wg);
-            const size_t lds = static_cast<size_t>(2) * args.gtile * (lmax + 1) * csz;
+            const size_t lds = bufs + (args.gtw ? ntw * csz : 0);
             PSPFFT_LOG(3, "pass %d prec %d generic: %d problems in %d segments, %ld workgroups of 256 threads, "
                           "%d lines each, %zu B LDS", mode, prec, args.count, args.nseg, wg, args.gtile, lds);
             if (pspfft::launch_generic(mode, prec, args, static_cast<int>(wg), lds, stream) != hipSuccess)

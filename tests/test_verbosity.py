@@ -67,9 +67,9 @@ def test_each_level_adds_its_messages(captured, level):
     else:
         assert not info1
     if level >= ps.CONSOLE_INFO_2:
-        # one stage-plan line per axis: x = 15 points (5 x 3), y = 32 (16 x 2), z = 48 (24 x 2)
+        # one stage-plan line per axis: x = 15 points (one radix-15 stage), y = 32 (16 x 2), z = 48 (24 x 2)
         assert len(info2) >= 3
-        assert "axis x: n = 15, line of 15 points, stages 5 x 3, generic line kernel" in info2[0]
+        assert "axis x: n = 15, line of 15 points, stages 15, generic line kernel" in info2[0]
         assert "axis y: n = 16, line of 32 points, stages 16 x 2, radix-family kernels" in info2[1]
         assert "axis z: n = 24, line of 48 points, stages 24 x 2, radix-family kernels" in info2[2]
     else:

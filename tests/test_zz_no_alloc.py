@@ -72,3 +72,43 @@ def test_noalloc_refuses_meshes_beyond_its_array():
     assert _noalloc(lib, plan, S, S) == 2  # PSPFFT_ERR_UNSUPPORTED_SIZE, nothing enqueued
     assert lib.pspfft_solve_noalloc(None, None, None, None) == 1
     plan.close()
+
+
+def test_noalloc_solve_replays_from_a_captured_graph():
+    """The use the allocation-free solve is for: captured once into a HIP graph
+    (after one eager call, which looks up the array's address and sets kernel
+    attributes), then replayed on new sources written between the replays; every
+    replay equals the eager workspace solve of the same source, bit for bit."""
+    import paper_1106_0557_amd as ps
+    from paper_1106_0557_amd import _lib
+
+    lib = _lib.load()
+    n = (64, 64, 48)
+    h = tuple(1.0 / v for v in n)
+    plan = ps.Plan(*n, h=h, dtype=torch.float32)
+    S = sources.random_field(n, seed=90).to("cuda", torch.float32)
+    out = torch.empty_like(S)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        _lib.check(_noalloc(lib, plan, S, out), "pspfft_solve_noalloc")  # eager first call
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        _lib.check(_noalloc(lib, plan, S, out), "pspfft_solve_noalloc (captured)")
+    ws = plan.workspace()
+    for k in range(3):
+        S.copy_(sources.random_field(n, seed=91 + k).to("cuda", torch.float32))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        want = ws.solve(S)
+        torch.cuda.synchronize()
+        say(f"[noalloc graph] replay {k}")
+        assert torch.equal(out, want), f"replay {k} differs from the eager solve"
+    ref = oracle.solve_fft(S.double().cpu().numpy(), h)
+    assert norms.rel_l2(out.double().cpu().numpy(), ref) <= 1e-5
+    del g
+    ws.close()
+    plan.close()
