@@ -129,7 +129,8 @@ pspfft_verbosity pspfft_get_verbosity(void);
 
 /* Receiver of messages: level, the text (no newline; valid during the call) and
  * the user pointer given to pspfft_set_log_callback.  May be called from any
- * thread that calls the library, one message at a time. */
+ * thread that calls the library, one message at a time (under a library lock:
+ * the receiver must not call back into the library). */
 typedef void (*pspfft_log_fn)(pspfft_verbosity level, const char *message, void *user);
 /* Send messages to fn instead of stderr; NULL goes back to stderr. */
 pspfft_status pspfft_set_log_callback(pspfft_log_fn fn, void *user);

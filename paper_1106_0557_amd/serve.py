@@ -479,6 +479,27 @@ def replay_plain(sizes_arrivals, srcs, dtype=None, realtime=True, log=print):
             "latency_ms_p99": percentile(lat_ms, 99), "latency_ms_max": max(lat_ms), "wall_s": wall}
 
 
+class _NoGC:
+    """Python's cyclic garbage collector paused over a timed trace (collected
+    just before), as a serving process tunes it: a full collection over the
+    trace's thousands of request objects stalls the scheduler for milliseconds."""
+
+    def __enter__(self):
+        import gc
+
+        gc.collect()
+        self._was = gc.isenabled()
+        gc.disable()
+        return self
+
+    def __exit__(self, *exc):
+        import gc
+
+        if self._was:
+            gc.enable()
+        return False
+
+
 def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, count: int = 2000,
                  budget_frac: float = 0.8, max_inflight: int = 64, small_budget: int = 2 << 30,
                  plain_dtype=None):
@@ -533,10 +554,11 @@ def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, 
         # closed loop: all requests present at t = 0
         srv = Server(ex, budget, max_inflight=max_inflight)
         reqs = make(0.0)  # the clients' side, before the clock starts
-        t0 = time.perf_counter()
-        fin = srv.run_trace(reqs, realtime=False)
-        ex.synchronize()
-        wall = time.perf_counter() - t0
+        with _NoGC():
+            t0 = time.perf_counter()
+            fin = srv.run_trace(reqs, realtime=False)
+            ex.synchronize()
+            wall = time.perf_counter() - t0
         sat = summarize(fin, wall)
         # accuracy: the first request of each size against the FP64 GPU solve
         import paper_1106_0557_amd as ps
@@ -558,10 +580,11 @@ def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, 
         rate = 0.7 * sat["solves_per_s"]
         srv = Server(ex, budget, max_inflight=max_inflight)
         reqs = make(1.0 / rate)
-        t0 = time.perf_counter()
-        fin = srv.run_trace(reqs, realtime=True)
-        ex.synchronize()
-        op = summarize(fin, time.perf_counter() - t0)
+        with _NoGC():
+            t0 = time.perf_counter()
+            fin = srv.run_trace(reqs, realtime=True)
+            ex.synchronize()
+            op = summarize(fin, time.perf_counter() - t0)
         del fin, reqs
         log(f"[serve] {name}: Poisson {rate:.0f}/s: p50 {op['latency_ms_p50']:.3f} ms, "
             f"p99 {op['latency_ms_p99']:.3f} ms")
@@ -571,10 +594,11 @@ def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, 
         torch.cuda.synchronize()
         srv = Server(ex, small_budget, max_inflight=max_inflight)
         reqs = make(1.0 / rate)
-        t0 = time.perf_counter()
-        fin = srv.run_trace(reqs, realtime=True)
-        ex.synchronize()
-        small = summarize(fin, time.perf_counter() - t0)
+        with _NoGC():
+            t0 = time.perf_counter()
+            fin = srv.run_trace(reqs, realtime=True)
+            ex.synchronize()
+            small = summarize(fin, time.perf_counter() - t0)
         small.update({"budget_bytes": small_budget, "max_used_bytes": srv.max_used})
         del fin, reqs
         log(f"[serve] {name}: budget {small_budget >> 20} MiB: {small['solves_per_s']:.0f} solves/s, "
@@ -592,7 +616,8 @@ def bench_served(n: int = 128, dtype=None, log=print, sizes=None, weights=None, 
         del srcs
         torch.cuda.synchronize()
         arrivals = [(r.n, r.arrival / rate) for r in trace]
-        plain = replay_plain(arrivals, srcs64, dtype=plain_dtype, realtime=True)
+        with _NoGC():
+            plain = replay_plain(arrivals, srcs64, dtype=plain_dtype, realtime=True)
         log(f"[serve] {name}: plain {str(plain_dtype).split('.')[-1]} at {rate:.0f}/s: "
             f"{plain['solves_per_s']:.0f} solves/s, p50 {plain['latency_ms_p50']:.3f} ms, "
             f"p99 {plain['latency_ms_p99']:.3f} ms")
