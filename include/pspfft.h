@@ -246,11 +246,15 @@ pspfft_status pspfft_solve_ws(pspfft_plan_t plan, pspfft_workspace_t ws, const v
 /*
  * Solve `count` independent problems.  plans[i], ws[i], S[i], Phi[i] describe
  * problem i; plans may differ in size and precision; each ws[i] must belong to
- * plans[i] and be distinct from every other ws[j].  Each pass is issued as one
- * launch per group of problems sharing a precision and a radix family (at most
- * 32 problems per launch), so a batch of mixed sizes costs a handful of launches
- * per pass.  Results do not depend on what else is in the batch: every problem
- * is cut into the same tiles whatever its neighbours.
+ * plans[i] and be distinct from every other ws[j].  Every argument is checked
+ * before anything is enqueued.  The problems of one plan go through the five
+ * passes together, one launch per pass (at most 32 problems per launch); when
+ * the batch holds several plans, each plan's problems run on a stream of the
+ * library's own (8 per device, default priority), side by side, forked from and
+ * joined back into `stream` by events: the batch is ordered after the work
+ * queued on `stream` before the call and before the work queued after it, as
+ * if it ran on `stream`.  Results do not depend on what else is in the batch:
+ * every problem is cut into the same tiles whatever its neighbours.
  */
 pspfft_status pspfft_solve_batched(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
                                    const void *const *S, void *const *Phi, hipStream_t stream);

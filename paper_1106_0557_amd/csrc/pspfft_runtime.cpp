@@ -698,6 +698,10 @@ pspfft_status run_pass(int mode, int count, const pspfft_plan_t *plans, const ps
 
 pspfft_status solve_all(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws, const void *const *S,
                         void *const *Phi, hipStream_t stream);
+pspfft_status check_batch(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws, const void *const *S,
+                          void *const *Phi);
+pspfft_status solve_forked(const std::vector<std::vector<int>> &groups, const pspfft_plan_t *plans,
+                           const pspfft_workspace_t *ws, const void *const *S, void *const *Phi, hipStream_t stream);
 
 }  // namespace
 
@@ -954,25 +958,126 @@ pspfft_status pspfft_pass_batched(pspfft_pass pass, int count, const pspfft_plan
 
 pspfft_status pspfft_solve_batched(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
                                    const void *const *S, void *const *Phi, hipStream_t stream) {
-    return solve_all(count, plans, ws, S, Phi, stream);
+    pspfft_status st = check_batch(count, plans, ws, S, Phi);
+    if (st != PSPFFT_OK) return st;
+    // problems of one plan form a group; several groups run side by side
+    std::vector<pspfft_plan_t> keys;
+    std::vector<std::vector<int>> groups;
+    for (int i = 0; i < count; ++i) {
+        size_t g = 0;
+        while (g < keys.size() && keys[g] != plans[i]) ++g;
+        if (g == keys.size()) {
+            keys.push_back(plans[i]);
+            groups.emplace_back();
+        }
+        groups[g].push_back(i);
+    }
+    if (groups.size() < 2) return solve_all(count, plans, ws, S, Phi, stream);
+    return solve_forked(groups, plans, ws, S, Phi, stream);
 }
 
 }  // extern "C"
 
 namespace {
-pspfft_status solve_all(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws, const void *const *S,
-                        void *const *Phi, hipStream_t stream) {
+// Every argument of a batch of whole solves, checked before anything is
+// enqueued: plans and their own distinct workspaces, sources and potentials
+// present and aligned to two reals.
+pspfft_status check_batch(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws, const void *const *S,
+                          void *const *Phi) {
+    const pspfft_status bad = PSPFFT_ERR_INVALID_ARGUMENT;
     if (count < 0 || (count > 0 && (!plans || !ws || !S || !Phi)))
-        return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_solve_batched: count %d or null array", count);
-    for (int i = 0; i < count; ++i)
+        return fail(bad, -1, "pspfft_solve_batched: count %d or null array", count);
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !ws[i] || ws[i]->plan != plans[i])
+            return fail(bad, plans[i] ? plans[i]->verbosity : -1, "pspfft_solve_batched: problem %d: null plan or "
+                        "workspace, or a workspace of another plan", i);
+        const uintptr_t al = 2 * real_size(plans[i]->prec);
+        if (!S[i] || !Phi[i] || reinterpret_cast<uintptr_t>(S[i]) % al || reinterpret_cast<uintptr_t>(Phi[i]) % al)
+            return fail(bad, plans[i]->verbosity, "pspfft_solve_batched: problem %d: source or potential null or not "
+                        "aligned to two reals", i);
         for (int j = i + 1; j < count; ++j)
             if (ws[i] == ws[j])
-                return fail(PSPFFT_ERR_INVALID_ARGUMENT, -1, "pspfft_solve_batched: problems %d and %d share a workspace", i, j);
-    for (int mode = pspfft::X_FWD; mode <= pspfft::X_INV; ++mode) {
-        pspfft_status st = run_pass(mode, count, plans, ws, S, Phi, stream);
-        if (st != PSPFFT_OK) return st;
+                return fail(bad, -1, "pspfft_solve_batched: problems %d and %d share a workspace", i, j);
     }
     return PSPFFT_OK;
+}
+
+pspfft_status solve_all(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws, const void *const *S,
+                        void *const *Phi, hipStream_t stream) {
+    pspfft_status st = check_batch(count, plans, ws, S, Phi);
+    for (int mode = pspfft::X_FWD; st == PSPFFT_OK && mode <= pspfft::X_INV; ++mode)
+        st = run_pass(mode, count, plans, ws, S, Phi, stream);
+    return st;
+}
+
+// Streams and events for batches that run several plans side by side: per
+// device, kForkStreams non-blocking streams of default priority and a ring of
+// events, created on first use.  A fork records an event on the caller's
+// stream that every group's stream waits for, enqueues each group's five
+// passes on its stream, and makes the caller's stream wait for each stream's
+// last event, so the batch is ordered after the caller's earlier work and
+// before its later work, as on one stream.  (A wait takes the event as recorded
+// at the time of the call, so reusing the ring's events later is safe.)
+constexpr int kForkStreams = 8;
+constexpr int kForkEvents = 64;
+struct ForkPool {
+    std::mutex mu;
+    hipStream_t streams[kForkStreams] = {};
+    hipEvent_t events[kForkEvents] = {};
+    int next = 0;
+    bool ready = false;
+};
+ForkPool g_fork[64];
+
+pspfft_status solve_forked(const std::vector<std::vector<int>> &groups, const pspfft_plan_t *plans,
+                           const pspfft_workspace_t *ws, const void *const *S, void *const *Phi, hipStream_t stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(PSPFFT_ERR_DEVICE, -1, "pspfft_solve_batched: hipGetDevice");
+    ForkPool &fp = g_fork[dev];
+    std::lock_guard<std::mutex> lk(fp.mu);
+    if (!fp.ready) {
+        for (auto &q : fp.streams)
+            if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess)
+                return fail(PSPFFT_ERR_DEVICE, -1, "pspfft_solve_batched: stream creation");
+        for (auto &e : fp.events)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                return fail(PSPFFT_ERR_DEVICE, -1, "pspfft_solve_batched: event creation");
+        fp.ready = true;
+    }
+    auto event = [&]() {
+        hipEvent_t e = fp.events[fp.next];
+        fp.next = (fp.next + 1) % kForkEvents;
+        return e;
+    };
+    const hipEvent_t start = event();
+    if (hipEventRecord(start, stream) != hipSuccess) return fail(PSPFFT_ERR_DEVICE, -1, "pspfft_solve_batched: fork");
+    const int nused = static_cast<int>(std::min<size_t>(groups.size(), kForkStreams));
+    for (int k = 0; k < nused; ++k)
+        if (hipStreamWaitEvent(fp.streams[k], start, 0) != hipSuccess)
+            return fail(PSPFFT_ERR_DEVICE, -1, "pspfft_solve_batched: fork");
+    pspfft_status st = PSPFFT_OK;
+    for (size_t g = 0; g < groups.size() && st == PSPFFT_OK; ++g) {
+        std::vector<pspfft_plan_t> p;
+        std::vector<pspfft_workspace_t> w;
+        std::vector<const void *> s;
+        std::vector<void *> f;
+        for (int i : groups[g]) {
+            p.push_back(plans[i]);
+            w.push_back(ws[i]);
+            s.push_back(S[i]);
+            f.push_back(Phi[i]);
+        }
+        st = solve_all(static_cast<int>(p.size()), p.data(), w.data(), s.data(), f.data(),
+                       fp.streams[g % kForkStreams]);
+    }
+    // join every stream that took work, whatever happened above
+    for (int k = 0; k < nused; ++k) {
+        const hipEvent_t done = event();
+        if (hipEventRecord(done, fp.streams[k]) != hipSuccess || hipStreamWaitEvent(stream, done, 0) != hipSuccess)
+            st = fail(PSPFFT_ERR_DEVICE, -1, "pspfft_solve_batched: join");
+    }
+    return st;
 }
 }  // namespace
 

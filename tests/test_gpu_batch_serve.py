@@ -195,3 +195,35 @@ def test_plan_bytes_before_and_after_the_first_solve():
         torch.cuda.synchronize()
         assert p.resident_bytes == want + p.workspace_bytes
         p.close()
+
+
+def test_batch_of_several_plans_keeps_the_callers_stream_order():
+    """A batch of several plans runs its groups on the library's own streams; it
+    must still start after the caller's earlier work on the stream (sources
+    written by a long chain of kernels just before the call) and end before the
+    caller's later work (copies of the potentials queued just after it)."""
+    import paper_1106_0557_amd as ps
+
+    say("[batch fork] stream order")
+    meshes = [(32, 32, 32), (48, 48, 48), (24, 20, 16), (64, 64, 64), (60, 30, 15)]
+    plans = [ps.Plan(*n, h=(0.1, 0.2, 0.3), dtype=torch.float32) for n in meshes]
+    ws = [p.workspace() for p in plans]
+    base = [sources.random_field(n, seed=200 + k).to("cuda", torch.float32) for k, n in enumerate(meshes)]
+    torch.cuda.synchronize()
+    big = torch.randn(2048, 2048, device="cuda")
+    for _ in range(20):
+        big = big @ big
+        big = big / big.norm()
+    S = [b + 0.0 * big[0, 0] for b in base]  # written only after the chain
+    P = [torch.empty_like(s) for s in S]
+    ps.solve_batched(ws, S, P)
+    copies = [p.clone() for p in P]  # queued right after the batch on the same stream
+    torch.cuda.synchronize()
+    for k, n in enumerate(meshes):
+        alone = plans[k].solve(base[k])
+        torch.cuda.synchronize()
+        assert torch.equal(copies[k], alone), f"problem {k} {n}: batch not ordered with the caller's stream"
+    for w in ws:
+        w.close()
+    for p in plans:
+        p.close()
