@@ -87,6 +87,7 @@ class GpuExecutor:
         self._pending: set = set()      # steps issued and not yet seen complete
         self._launches = 0              # launches of the step being built
         self._step_events: List[Any] = []
+        self._step_ready: List[Any] = []  # admission marks of the step being built
         self._events: List[Any] = []  # recycled events
         self._ws_bytes: Dict[Any, int] = {}  # workspace bytes per mesh
 
@@ -163,18 +164,22 @@ class GpuExecutor:
     def alloc_output(self, req: Request):
         return self.torch.empty(req.S.shape, dtype=self.dtype, device=req.S.device)
 
-    def admitted(self, req: Request) -> None:
-        """Mark the caller's stream at admission: the source was produced there,
-        and the workspace and output were allocated there.  The request's first
-        launch, on a stream of the pool, waits for this mark."""
+    def admitted(self, reqs: Sequence[Request]) -> None:
+        """Mark the caller's stream once the requests admitted in one scheduler
+        step have their workspaces and outputs (allocated there) and their
+        sources (produced there before submission).  Their first launches, on
+        streams of the pool, wait for this one mark."""
         ev = self._event()
         ev.record(self.torch.cuda.current_stream(self.device))
-        req._ready = ev
+        self._step_ready.append(ev)
+        for r in reqs:
+            r._ready = ev
 
     # ------------------------------------------------------------ launches
     def begin_step(self) -> None:
         self._launches = 0
-        self._step_events = []
+        self._step_events = self._step_ready  # the admission marks retire with this step
+        self._step_ready = []
 
     def _pointers(self, req: Request):
         """Launch arguments of an admitted request, checked once."""
@@ -193,8 +198,9 @@ class GpuExecutor:
         cols = ([], [], [], [])
         for r in reqs:
             if r._ready is not None:  # first launch: after the caller's work on its stream
-                s.wait_event(r._ready)
-                self._step_events.append(r._ready)  # recycled with this step's events
+                if id(r._ready) not in waited:
+                    waited.add(id(r._ready))
+                    s.wait_event(r._ready)
                 r._ready = None
             if r._dep is not None:
                 ev, step = r._dep
@@ -291,6 +297,7 @@ class Server:
         self.waiting.append(req)
 
     def _admit(self) -> None:
+        new = []
         while self.waiting and len(self.inflight) < self.max_inflight:
             req = self.waiting[0]
             reuse = self.ex.has_pooled(req)
@@ -305,9 +312,7 @@ class Server:
             self.waiting.popleft()
             req._ws = self.ex.acquire(req)  # creates the plan if it is new; it stays counted in `used`
             req.phi = self.ex.alloc_output(req)
-            admitted = getattr(self.ex, "admitted", None)
-            if admitted is not None:
-                admitted(req)
+            new.append(req)
             self.used += need
             self.max_used = max(self.max_used, self.used)
             active = getattr(self.ex, "active_passes", None)
@@ -315,6 +320,9 @@ class Server:
             req.next_pass = req.passes[0]
             req.t_admit = self.now()
             self.inflight.append(req)
+        admitted = getattr(self.ex, "admitted", None)
+        if new and admitted is not None:
+            admitted(new)
 
     # -------------------------------------------------------------- stepping
     def _finish(self, token, reqs) -> None:

@@ -37,6 +37,7 @@ class FakeExecutor:
         self.step_no = 0
         self.created = 0
         self.plans = set()     # meshes with a resident plan
+        self.admissions = 0    # calls of admitted(): one per scheduler step that admits
 
     def plan_bytes(self, req):
         nx, ny, nz = req.n
@@ -48,8 +49,10 @@ class FakeExecutor:
     def resident_bytes(self):
         return sum(32 * (n[0] + 1) * (n[1] + 1) * (n[2] + 1) for (n, _) in self.plans)
 
-    def admitted(self, req):
-        self.events.append(("admit", req.index))
+    def admitted(self, reqs):
+        self.admissions += 1
+        for r in reqs:
+            self.events.append(("admit", r.index))
 
     def workspace_bytes(self, req):
         nx, ny, nz = req.n
@@ -309,3 +312,5 @@ def test_each_request_is_marked_at_admission_before_its_first_pass():
         seq = [k for k, (what, r) in enumerate(ex.events) if r == i]
         kinds = [ex.events[k][0] for k in seq]
         assert kinds[0] == "admit" and kinds.count("admit") == 1 and "pass" in kinds[1:]
+    # one mark per admitting step, not per request (3 admitted at once at the start)
+    assert ex.admissions < 6
