@@ -192,11 +192,50 @@ __host__ __device__ constexpr int pass_tile(int prec, int mode, int E, int nb) {
     return t;
 }
 
+// Lines per workgroup of the wavefront-owned column kernel for lines of NB
+// threads, ST compile-time stages: three-stage lines take the default tile;
+// four-stage ones (1152 and 2304 points in the 36-family, 640 and 1280 in the
+// 20-family; FP32) halve it while the workgroup exceeds the family's largest or
+// the tile's rows and the stage twiddles exceed the LDS.
+__host__ __device__ constexpr int wave_tile(int prec, int mode, int E, int NB, int ST = 3) {
+    int t = fix_tile(prec, mode, NB);
+    if (ST != 4) return t;
+    const long L = static_cast<long>(E) * NB, csz = prec == 0 ? 8 : 16;
+    while (t > 1 && (static_cast<long>(t) * NB > max_block_for(prec, E) ||
+                     (t * static_cast<long>(wave_line_stride(static_cast<int>(L))) + L - 1) * csz > 160 * 1024))
+        t /= 2;
+    return t;
+}
+
+// Whether the wavefront-owned column kernel keeps the stage twiddles in LDS
+// after the tile's rows: always for three-stage lines; for four-stage ones
+// unless leaving them in global memory (a table the L1 holds) lets one more
+// workgroup share a CU.
+__host__ __device__ constexpr bool wave_tw_lds(int prec, int mode, int E, int NB, int ST = 3) {
+    if (ST != 4) return true;
+    const long L = static_cast<long>(E) * NB, csz = prec == 0 ? 8 : 16, cap = 160 * 1024;
+    const long rows = wave_tile(prec, mode, E, NB, ST) * static_cast<long>(wave_line_stride(static_cast<int>(L))) * csz;
+    return cap / rows <= cap / (rows + (L - 1) * csz);
+}
+
 // LDS bytes of the wavefront-owned column kernel of pass `mode` for lines of
-// length L = E*NB: one row per line of the tile, then the stage twiddles.
-__host__ __device__ constexpr size_t wave_lds_bytes(int prec, int mode, int E, int NB) {
+// length L = E*NB: one row per line of the tile, then the stage twiddles (when
+// they are kept in LDS).
+__host__ __device__ constexpr size_t wave_lds_bytes(int prec, int mode, int E, int NB, int ST = 3) {
     const int L = E * NB;
-    return static_cast<size_t>(fix_tile(prec, mode, NB) * wave_line_stride(L) + L - 1) * (prec == 0 ? 8 : 16);
+    return static_cast<size_t>(wave_tile(prec, mode, E, NB, ST) * wave_line_stride(L) +
+                               (wave_tw_lds(prec, mode, E, NB, ST) ? L - 1 : 0)) *
+           (prec == 0 ? 8 : 16);
+}
+
+// Wavefronts per SIMD the wavefront-owned kernel is compiled for: as many as
+// its workgroups that fit a CU's LDS bring (so that the register allocation
+// does not keep a second workgroup out), at least one.
+__host__ __device__ constexpr int wave_waves_per_simd(int prec, int mode, int E, int NB, int ST = 3) {
+    if (ST != 4) return 1;
+    const long per_cu = 160L * 1024 / static_cast<long>(wave_lds_bytes(prec, mode, E, NB, ST));
+    const long w = per_cu * wave_tile(prec, mode, E, NB, ST) * NB / 64 / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : static_cast<int>(w));
 }
 __host__ __device__ constexpr size_t wave_z_lds_bytes(int prec, int E, int NB) {
     return wave_lds_bytes(prec, Z_CONV, E, NB);

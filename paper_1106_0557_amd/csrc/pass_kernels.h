@@ -28,6 +28,25 @@
 
 namespace pspfft {
 
+// Global-address-space view of a pointer that came from device memory (the
+// compiler cannot infer it), so its loads are global rather than flat ones.
+template <typename U>
+using gbl = __attribute__((address_space(1))) U;
+template <typename U>
+__device__ __forceinline__ const gbl<U> *as_global(const U *p) {
+    return (const gbl<U> *)p;
+}
+
+// Stage twiddle w of a table in LDS (a generic pointer) or in global memory.
+template <typename T>
+__device__ __forceinline__ cx<T> tw_at(const cx<T> *p, int i) {
+    return p[i];
+}
+template <typename T>
+__device__ __forceinline__ cx<T> tw_at(const gbl<cx<T>> *p, int i) {
+    return cx<T>{p[i].x, p[i].y};
+}
+
 // CNB, CLDSW: threads per line and LDS stride when known at compile time (a
 // two-stage line, L = E*K and CNB = K; three stages with radices E, M, K,
 // L = E*M*K and CNB = M*K; or four, E, M, M, K, L = E*M*M*K and CNB = M*M*K),
@@ -66,8 +85,8 @@ struct LineFFT {
     // twiddle table.  TW: multiply by twiddles (every stage but the first).
     // TO_LDS: scatter the outputs to their Stockham positions in LDS; otherwise
     // (last stage) they land in the thread's own positions, in registers.
-    template <int R, bool TW, bool TO_LDS, int CNS = 0>
-    static __device__ __forceinline__ void stage(cx<T> *v, int Ns_, uint32_t mg, const cx<T> *tw, cx<T> *lds,
+    template <int R, bool TW, bool TO_LDS, int CNS = 0, typename TP = const cx<T> *>
+    static __device__ __forceinline__ void stage(cx<T> *v, int Ns_, uint32_t mg, TP tw, cx<T> *lds,
                                                  int ldsw_, int c, int t, int NB_) {
         constexpr int NBF = E / R;
         const int NB = CNB ? CNB : NB_;
@@ -88,10 +107,10 @@ struct LineFFT {
                 x[r] = v[i + r * NBF];
             });
             if constexpr (TW) {
-                const cx<T> *twk = tw + k * (R - 1);
+                const TP twk = tw + k * (R - 1);
                 sfor<1, R>([&](auto rc) {
                     constexpr int r = decltype(rc)::value;
-                    const cx<T> w = twk[r - 1];
+                    const cx<T> w = tw_at(twk, r - 1);
                     if constexpr (DIR > 0) x[r] = cmulc(x[r], w);
                     else x[r] = cmul(x[r], w);
                 });
@@ -134,7 +153,8 @@ struct LineFFT {
 
     // Transform the line whose positions t + NB*m the thread holds in v[m].
     // K = radix of the last stage (1: the whole line is one radix-E stage).
-    // twl: stage twiddle tables in LDS, published by the first barrier.
+    // twl: stage twiddle tables in LDS, published by the first barrier (or in
+    // global memory: a global-address-space pointer).
     // LEAD: open with a barrier so that earlier readers of the line's LDS
     // region are done; a caller that has just passed a barrier can skip it.
     // WAVE: every line lies within one wavefront (its LDS region too), so the
@@ -146,9 +166,9 @@ struct LineFFT {
         else __syncthreads();
     }
 
-    template <int K, bool LEAD = true, bool WAVE = false>
+    template <int K, bool LEAD = true, bool WAVE = false, typename TP = const cx<T> *>
     static __device__ __forceinline__ void run(cx<T> *v, const AxisPlan &ax, cx<T> *lds, int ldsw,
-                                               const cx<T> *twl, int c, int t) {
+                                               TP twl, int c, int t) {
         const int NB = CNB ? CNB : ax.NB;
         if constexpr (K == 1) {
             stage<E, false, false>(v, 1, 0u, twl, lds, ldsw, c, t, NB);
@@ -246,14 +266,6 @@ __device__ __forceinline__ void copy_to_lds(cx<T> *dst, const void *src, int cou
     for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = s[i];
 }
 
-// Global-address-space view of a pointer that came from device memory (the
-// compiler cannot infer it), so its loads are global rather than flat ones.
-template <typename U>
-using gbl = __attribute__((address_space(1))) U;
-template <typename U>
-__device__ __forceinline__ const gbl<U> *as_global(const U *p) {
-    return (const gbl<U> *)p;
-}
 
 // Element m of a line: base + lane + m*step bytes.  OFF32 (set by the host when
 // every array of the launch is below 4 GB): the offset lane + m*step is
@@ -277,6 +289,21 @@ __device__ __forceinline__ LinePtr<T, OFF32> line_ptr(const void *base, size_t l
                                                       size_t esz) {
     return LinePtr<T, OFF32>{const_cast<char *>(static_cast<const char *>(base)), lane_elems * esz, step_elems * esz};
 }
+
+// Element m of a line in an array of 4 GB or more whose lane offsets stay below
+// the position stride (z lines: a lane's offset within its NB-position block):
+// a workgroup-uniform 64-bit base per position block, base + m*step, plus one
+// 32-bit lane offset.
+template <typename T>
+struct LinePtrW {
+    char *base;
+    size_t lane;
+    size_t step;
+    __device__ __forceinline__ char *block(int m) const { return base + static_cast<size_t>(m) * step; }
+    __device__ __forceinline__ cx<T> &operator[](int m) const {
+        return *reinterpret_cast<cx<T> *>(block(m) + static_cast<uint32_t>(lane));
+    }
+};
 
 // fix_stages(FIX) (2, 3 or 4): every problem of the launch has lines of that
 // many stages with radices E, (M, (M,)) K and the workgroup holds pass_tile()
@@ -614,9 +641,12 @@ __device__ __forceinline__ void buffer_store(const cx<T> v, char *base, uint32_t
 
 // One z line of a compile-time Z_CONV launch for lane (c, t) of the tile that
 // virtual workgroup `bid` handles: the same decomposition as pass_kernel's.
-template <typename T>
+// WIDE (z lines of arrays of 4 GB or more): 64-bit bases per position block
+// (LinePtrW), `bytes` is the position stride (a lane's offset stays below it),
+// and g points at the line's own spectrum run.
+template <typename T, bool WIDE = false>
 struct ZLine {
-    LinePtr<T, true> lane;  // positions t + NB*m of the line in W (or Wn)
+    std::conditional_t<WIDE, LinePtrW<T>, LinePtr<T, true>> lane;  // positions t + NB*m in W (or Wn)
     const gbl<const char> *g;  // spectrum octant (G, or Gn for the Nyquist column)
     uint32_t glo, ghi, gstep;  // byte offsets of positions t + NB*m (m < E/2) and NB*(E-m) - t
     uint32_t bytes;            // size of the line's array (W or Wn)
@@ -625,8 +655,8 @@ struct ZLine {
 
 // GZ: the spectrum is stored kz-fastest (octant index (kyo*nx + kx)*(nz+1) + kz,
 // Nyquist column kyo*(nz+1) + kz), for lanes that walk along a line.
-template <typename T, int E, int NB, int TILE, bool GZ = false>
-__device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int c, int t) {
+template <typename T, int E, int NB, int TILE, bool GZ = false, bool WIDE = false>
+__device__ __forceinline__ ZLine<T, WIDE> z_line(const LaunchArgs &args, int bid, int c, int t) {
     constexpr int CSZ = static_cast<int>(sizeof(cx<T>));
     int sgi = 0;
     while (sgi + 1 < args.nseg && bid >= args.seg[sgi + 1].wg_begin) ++sgi;
@@ -644,7 +674,7 @@ __device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int 
     const bool nyq = local >= sg.wg_main;
     if (nyq) local -= sg.wg_main;
     const int g = local * TILE + c;
-    ZLine<T> zl;
+    ZLine<T, WIDE> zl;
     int ky, kx;
     size_t lane_off;
     const void *arr;
@@ -661,16 +691,28 @@ __device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int 
         const int sh = __builtin_ctz(static_cast<unsigned>(zb));
         lane_off = static_cast<size_t>(ky) * zb * nx + kx +
                    (static_cast<size_t>(t >> sh) * 2 * ny * zb + (t & (zb - 1))) * nx;
-        zl.lane = line_ptr<T, true>(arr, zl.active ? lane_off : 0, static_cast<size_t>(NB) * 2 * ny * nx, CSZ);
-        zl.bytes = static_cast<uint32_t>(static_cast<size_t>(pl.nz) * 2 * ny * nx * CSZ);
+        if constexpr (WIDE) {
+            zl.lane = LinePtrW<T>{const_cast<char *>(static_cast<const char *>(arr)),
+                                  (zl.active ? lane_off : 0) * CSZ, static_cast<size_t>(NB) * 2 * ny * nx * CSZ};
+            zl.bytes = static_cast<uint32_t>(zl.lane.step);
+        } else {
+            zl.lane = line_ptr<T, true>(arr, zl.active ? lane_off : 0, static_cast<size_t>(NB) * 2 * ny * nx, CSZ);
+            zl.bytes = static_cast<uint32_t>(static_cast<size_t>(pl.nz) * 2 * ny * nx * CSZ);
+        }
     } else {
         zl.active = g < 2 * ny;
         ky = g;
         kx = nx;
         arr = pa.Wn;
         lane_off = static_cast<size_t>(g) + static_cast<size_t>(t) * 2 * ny;
-        zl.lane = line_ptr<T, true>(arr, zl.active ? lane_off : 0, static_cast<size_t>(NB) * 2 * ny, CSZ);
-        zl.bytes = static_cast<uint32_t>(static_cast<size_t>(pl.nz) * 2 * ny * CSZ);
+        if constexpr (WIDE) {
+            zl.lane = LinePtrW<T>{const_cast<char *>(static_cast<const char *>(arr)),
+                                  (zl.active ? lane_off : 0) * CSZ, static_cast<size_t>(NB) * 2 * ny * CSZ};
+            zl.bytes = static_cast<uint32_t>(zl.lane.step);
+        } else {
+            zl.lane = line_ptr<T, true>(arr, zl.active ? lane_off : 0, static_cast<size_t>(NB) * 2 * ny, CSZ);
+            zl.bytes = static_cast<uint32_t>(static_cast<size_t>(pl.nz) * 2 * ny * CSZ);
+        }
     }
     // G~ is even in ky and kz: octant index min(k, 2n - k)
     const int kyo = ky <= ny ? ky : 2 * ny - ky;
@@ -682,6 +724,11 @@ __device__ __forceinline__ ZLine<T> z_line(const LaunchArgs &args, int bid, int 
     } else {
         gb = nyq ? static_cast<size_t>(kyo) : static_cast<size_t>(kyo) * nx + kx;
         gs = nyq ? static_cast<size_t>(ny + 1) : static_cast<size_t>(ny + 1) * nx;
+    }
+    if constexpr (WIDE && GZ) {
+        // the line's own run of the spectrum: offsets within it stay small
+        if (zl.active) zl.g += gb * sizeof(T);
+        gb = 0;
     }
     zl.glo = zl.active ? static_cast<uint32_t>((gb + t * gs) * sizeof(T)) : 0u;
     zl.ghi = zl.active ? static_cast<uint32_t>((gb + (NB - t) * gs) * sizeof(T)) : 0u;
@@ -730,7 +777,8 @@ __device__ __forceinline__ ZLine<T> y_line(const LaunchArgs &args, int bid, int 
 }
 
 // Column passes (Y_FWD, Z_CONV, Y_INV) for lines of 16, 32 or 64 threads
-// (radices E, M, K with M*K = NB): each line lies within one wavefront
+// (ST = 3: radices E, M, K with M*K = NB; ST = 4: E, M, M, K with M*M*K = NB,
+// FP32 only, and a tile of wave_tile() lines): each line lies within one wavefront
 // (wavefront w holds lines w*64/NB onwards), so the stage exchanges stay inside
 // the wavefront and need no workgroup barrier.  The tile's stored half (all of
 // it for Y_INV) is loaded with adjacent lanes on adjacent lines (128-byte row
@@ -750,16 +798,21 @@ __device__ __forceinline__ ZLine<T> y_line(const LaunchArgs &args, int bid, int 
 // loop is entered with nothing outstanding, and plan fields are read through
 // the constant address space (scalar loads; a vector load there would wait for
 // the previous tile's stores).  Otherwise the workgroup takes one tile.
-template <typename T, int E, int K, int MODE, bool PERSIST>
-__global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) wave_col_kernel(const LaunchArgs args) {
+template <typename T, int E, int K, int MODE, bool PERSIST, int ST = 3, bool WIDE = false>
+__global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E)))
+__attribute__((amdgpu_waves_per_eu(wave_waves_per_simd(sizeof(T) == 4 ? 0 : 1, MODE, E,
+                                                       (ST == 4 ? (E & -E) * (E & -E) : (E & -E)) * K, ST))))
+wave_col_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
     static_assert(MODE == Y_FWD || MODE == Z_CONV || MODE == Y_INV, "column passes");
+    static_assert(ST == 3 || (ST == 4 && sizeof(T) == 4), "three-stage lines, or four-stage ones in FP32");
+    static_assert(!WIDE || MODE == Z_CONV, "64-bit bases for z lines only");
     constexpr int H = E / 2;
-    constexpr int NB = (E & -E) * K;
+    constexpr int NB = (ST == 4 ? (E & -E) * (E & -E) : (E & -E)) * K;
     static_assert(NB == 16 || NB == 32 || NB == 64, "lines of 16, 32 or 64 threads");
     constexpr int L = E * NB;
-    constexpr int TILE = fix_tile(sizeof(T) == 4 ? 0 : 1, MODE, NB);
+    constexpr int TILE = wave_tile(sizeof(T) == 4 ? 0 : 1, MODE, E, NB, ST);
     constexpr int S = wave_line_stride(L);
     constexpr int NLOAD = MODE == Y_INV ? E : H;   // forward transforms read the stored half
     constexpr int NSTORE = MODE == Y_FWD ? E : H;  // inverse ones keep the first half
@@ -774,20 +827,28 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) wa
     const int cc = tid & (TILE - 1), tc = tid >> __builtin_ctz(TILE);  // adjacent lanes on adjacent lines
     const int cw = tid >> __builtin_ctz(NB), tw = tid & (NB - 1);       // line cw lies in one wavefront
     const AxisPlan &ax0 = args.p[0].plan->ax[ZC ? 2 : 1];
-    cx<T> *twl = lds + TILE * S;
-    copy_to_lds<T>(twl, ax0.tw, ax0.ntw);  // published by the first barrier below
+    constexpr bool TWL = wave_tw_lds(sizeof(T) == 4 ? 0 : 1, MODE, E, NB, ST);
+    const auto twl = [&]() __attribute__((always_inline)) {
+        if constexpr (TWL) {
+            cx<T> *p = lds + TILE * S;
+            copy_to_lds<T>(p, ax0.tw, ax0.ntw);  // published by the first barrier below
+            return static_cast<const cx<T> *>(p);
+        } else {
+            return as_global(static_cast<const cx<T> *>(ax0.tw));
+        }
+    }();
     // position P = t + NB*m of a line's row sits at P + P/16 = t + t/16 + m*(NB + NB/16)
     constexpr int RM = NB + NB / 16;
     cx<T> *rowc = lds + cc * S + tc + (tc >> 4);
     cx<T> *roww = lds + cw * S + tw + (tw >> 4);
 
     auto line = [&](int b) __attribute__((always_inline)) {
-        if constexpr (ZC) return z_line<T, E, NB, TILE>(args, b, cc, tc);
+        if constexpr (ZC) return z_line<T, E, NB, TILE, false, WIDE>(args, b, cc, tc);
         else return y_line<T, NB, TILE>(args, b, cc, tc);
     };
     auto load_g = [&](int b, T *gv) __attribute__((always_inline)) {
         if constexpr (ZC) {
-            const ZLine<T> zl = z_line<T, E, NB, TILE, true>(args, b, cw, tw);
+            const ZLine<T, WIDE> zl = z_line<T, E, NB, TILE, true, WIDE>(args, b, cw, tw);
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 const uint32_t idx = m < H ? m : E - m - 1;
@@ -795,7 +856,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) wa
             }
         }
     };
-    ZLine<T> cur = line(bid);
+    auto cur = line(bid);
     T gnx[ZC ? E : 1];
     if constexpr (sizeof(T) == 4) {
         // the line first (loads retire in order: its rows can be written
@@ -831,7 +892,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) wa
         // FP64: the line is loaded after this tile's stores (the extra 16-byte
         // values held across the inverse transform do not stay in registers)
         constexpr bool PF = PERSIST && sizeof(T) == 4;
-        ZLine<T> fol = cur;
+        auto fol = cur;
         cx<T> nxt[PF ? NLOAD : 1];
         if constexpr (PERSIST) {
             fol = line(fbid);
@@ -849,9 +910,14 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) wa
         __syncthreads();  // results are in the rows
 #pragma unroll
         for (int m = 0; m < NSTORE; ++m) {
-            const uint32_t off = static_cast<uint32_t>(cur.lane.lane) +
-                                 static_cast<uint32_t>(m) * static_cast<uint32_t>(cur.lane.step);
-            buffer_store<T>(rowc[m * RM], cur.lane.base, cur.bytes, cur.active ? off : 0xfffffff0u);
+            if constexpr (WIDE) {
+                buffer_store<T>(rowc[m * RM], cur.lane.block(m), cur.bytes,
+                                cur.active ? static_cast<uint32_t>(cur.lane.lane) : 0xfffffff0u);
+            } else {
+                const uint32_t off = static_cast<uint32_t>(cur.lane.lane) +
+                                     static_cast<uint32_t>(m) * static_cast<uint32_t>(cur.lane.step);
+                buffer_store<T>(rowc[m * RM], cur.lane.base, cur.bytes, cur.active ? off : 0xfffffff0u);
+            }
         }
         if (!more) break;
         __syncthreads();  // the rows have been read
@@ -1093,17 +1159,17 @@ inline int zconv_persist_mode();
 
 // The wavefront-owned column kernel: persistent where one workgroup fills a
 // compute unit (zconv_persist_mode), otherwise one tile per workgroup.
-template <typename T, int E, int K, int MODE>
+template <typename T, int E, int K, int MODE, int ST = 3, bool WIDE = false>
 hipError_t launch_wave_col(const LaunchArgs &args, hipStream_t stream) {
     constexpr int kMaxDevices = 64;
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
-    constexpr int NB = (E & -E) * K;
-    constexpr int block = fix_tile(prec, MODE, NB) * NB;
-    constexpr size_t lds = wave_lds_bytes(prec, MODE, E, NB);
+    constexpr int NB = (ST == 4 ? (E & -E) * (E & -E) : (E & -E)) * K;
+    constexpr int block = wave_tile(prec, MODE, E, NB, ST) * NB;
+    constexpr size_t lds = wave_lds_bytes(prec, MODE, E, NB, ST);
     static_assert(lds <= 160 * 1024, "tile rows and twiddles fit the LDS");
     static int per_cu[kMaxDevices] = {0}, cus[kMaxDevices] = {0};
-    auto fp = wave_col_kernel<T, E, K, MODE, true>;
-    auto fo = wave_col_kernel<T, E, K, MODE, false>;
+    auto fp = wave_col_kernel<T, E, K, MODE, true, ST, WIDE>;
+    auto fo = wave_col_kernel<T, E, K, MODE, false, ST, WIDE>;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -1177,13 +1243,35 @@ hipError_t launch_kernel(const LaunchArgs &args, int grid, int block, size_t lds
 }
 
 // The wavefront-owned column kernel exists for three-stage lines of 16, 32 or 64
-// threads whose default tile fits the family's largest workgroup and the LDS.
-template <typename T, int E, int K, int MODE>
+// threads whose default tile fits the family's largest workgroup and the LDS,
+// and for four-stage FP32 lines of 32 or 64 threads (wave_tile() lines).
+template <typename T, int E, int K, int MODE, int ST = 3>
 constexpr bool wave_col_fits() {
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
-    constexpr int NB = (E & -E) * K;
-    return (NB == 16 || NB == 32 || NB == 64) && fix_tile(prec, MODE, NB) * NB <= max_block_for(prec, E) &&
-           wave_lds_bytes(prec, MODE, E, NB) <= 160 * 1024;
+    constexpr int M = E & -E;
+    if constexpr (ST == 4) {
+        constexpr int NB = M * M * K;
+        return prec == 0 && M < E && (NB == 32 || NB == 64) &&
+               wave_tile(prec, MODE, E, NB, 4) * NB <= max_block_for(prec, E) &&
+               wave_lds_bytes(prec, MODE, E, NB, 4) <= 160 * 1024;
+    } else {
+        constexpr int NB = M * K;
+        return (NB == 16 || NB == 32 || NB == 64) && fix_tile(prec, MODE, NB) * NB <= max_block_for(prec, E) &&
+               wave_lds_bytes(prec, MODE, E, NB) <= 160 * 1024;
+    }
+}
+
+// The y passes take the wavefront-owned kernel for three-stage lines where its
+// tile equals the column kernel's (pass_tile), from which the host counted the
+// launch's tiles.  Measured on 1152-point lines (576^3 FP32), four-stage y
+// lines lose 9 % in the forward pass and gain nothing in the inverse one.
+template <typename T, int E, int K, int MODE, int ST>
+constexpr bool wave_y_fits() {
+    constexpr int prec = sizeof(T) == 4 ? 0 : 1;
+    constexpr int M = E & -E;
+    constexpr int NB = (ST == 4 ? M * M : M) * K;
+    return ST == 3 && (NB == 32 || NB == 64) && wave_col_fits<T, E, K, MODE, ST>() &&
+           wave_tile(prec, MODE, E, NB, ST) == pass_tile(prec, MODE, E, NB);
 }
 
 template <typename T, int E, int K, int FIX>
@@ -1191,8 +1279,11 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
     switch (mode) {
         case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
         case Y_FWD:
-            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64) && wave_col_fits<T, E, K, Y_FWD>()) {
+            if constexpr (FIX == 3 && wave_y_fits<T, E, K, Y_FWD, 3>()) {
                 if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_FWD>(args, stream);
+            }
+            if constexpr (FIX == 4 && wave_y_fits<T, E, K, Y_FWD, 4>()) {
+                if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_FWD, 4>(args, stream);
             }
             if constexpr (FIX != 0) return launch_col<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
             else return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
@@ -1200,12 +1291,24 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
             if constexpr (FIX == 3 && wave_col_fits<T, E, K, Z_CONV>()) {
                 if (args.wave_z) return launch_wave_col<T, E, K, Z_CONV>(args, stream);
             }
+            if constexpr (FIX == 4 && wave_col_fits<T, E, K, Z_CONV, 4>()) {
+                if (args.wave_z) return launch_wave_col<T, E, K, Z_CONV, 4>(args, stream);
+            }
+            if constexpr (FIX == 3 + kFixWide && wave_col_fits<T, E, K, Z_CONV>()) {
+                if (args.wave_z) return launch_wave_col<T, E, K, Z_CONV, 3, true>(args, stream);
+            }
+            if constexpr (FIX == 4 + kFixWide && wave_col_fits<T, E, K, Z_CONV, 4>()) {
+                if (args.wave_z) return launch_wave_col<T, E, K, Z_CONV, 4, true>(args, stream);
+            }
             if (args.wave_z) return hipErrorInvalidValue;  // a kz-fastest spectrum needs wave_col_kernel
             if constexpr (FIX != 0) return launch_col<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
             else return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
         case Y_INV:
-            if constexpr (FIX == 3 && ((E & -E) * K == 32 || (E & -E) * K == 64) && wave_col_fits<T, E, K, Y_INV>()) {
+            if constexpr (FIX == 3 && wave_y_fits<T, E, K, Y_INV, 3>()) {
                 if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_INV>(args, stream);
+            }
+            if constexpr (FIX == 4 && wave_y_fits<T, E, K, Y_INV, 4>()) {
+                if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_INV, 4>(args, stream);
             }
             if constexpr (FIX != 0) return launch_col<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
             else return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);

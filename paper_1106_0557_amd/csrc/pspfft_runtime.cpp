@@ -374,17 +374,26 @@ bool arrays_below_4gb(pspfft_plan_t p) {
 // The z pass runs by wavefront-owned lines (wave_col_kernel) where its lines
 // have three stages E, M, K with M*K = 32 or 64 threads, or 16 threads where the
 // tile's rows take more than half the LDS (one workgroup per CU; measured, the
-// smaller 16-thread tiles gain nothing over the column kernel), the
-// compile-time instance exists and every array is below 4 GB.  Such plans keep
-// the spectrum kz-fastest, and their z launches always take that kernel.
+// smaller 16-thread tiles gain nothing over the column kernel), or four stages
+// in FP32 (E, M, M, K with 32 or 64 threads), and the compile-time instance
+// exists.  Arrays of 4 GB or more take its 64-bit form, which needs a z line's
+// NB-position block (NB*2ny*nx values) below 4 GB.  Such plans keep the
+// spectrum kz-fastest, and their z launches always take that kernel.
 bool z_wave_lines(pspfft_plan_t p) {
     const AxisPlan &az = p->host.ax[2];
     if (az.E == 0) return false;  // generic kernel
     const int prec = p->host.prec, M = az.E & -az.E, NB = az.NB;
+    const size_t block_bytes = static_cast<size_t>(NB) * 2 * p->n[1] * p->n[0] * (prec == 0 ? 8 : 16);
+    if (!arrays_below_4gb(p) && block_bytes >= (size_t(1) << 32) - 64) return false;
+    if (az.nst == 4)  // four-stage FP32 lines of 32 or 64 threads, wave_tile() lines per workgroup
+        return prec == 0 && M < az.E && az.R[1] == M && az.R[2] == M && M * M * az.R[3] == NB &&
+               (NB == 32 || NB == 64) &&
+               pspfft::wave_tile(prec, pspfft::Z_CONV, az.E, NB, 4) * NB <= pspfft::max_block_for(prec, az.E) &&
+               pspfft::wave_lds_bytes(prec, pspfft::Z_CONV, az.E, NB, 4) <= 160 * 1024;
     const bool nb_ok = NB == 32 || NB == 64 || (NB == 16 && pspfft::wave_z_lds_bytes(prec, az.E, NB) > 80 * 1024);
     return az.nst == 3 && az.R[1] == M && nb_ok && M * az.R[2] == NB &&
            pspfft::fix_tile(prec, pspfft::Z_CONV, NB) * NB <= pspfft::max_block_for(prec, az.E) &&
-           pspfft::fix_tile(prec, pspfft::Y_FWD, NB) * NB <= pspfft::max_block_for(prec, az.E) && arrays_below_4gb(p);
+           pspfft::fix_tile(prec, pspfft::Y_FWD, NB) * NB <= pspfft::max_block_for(prec, az.E);
 }
 
 // Lines (main, Nyquist) that a pass processes for one problem.
@@ -493,12 +502,14 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
         const pspfft_status st = launch_generic_lines(mode, gen, plans, ws, S, Phi, stream);
         if (st != PSPFFT_OK) return st;
     }
-    // One kernel per (precision, radix family E, last-stage radix K, spectrum layout).
+    // One kernel per (precision, radix family E, last-stage radix K, spectrum
+    // layout); a kz-fastest z group also shares its lines' stage count (the
+    // wavefront-owned kernel's tile depends on it).
     std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
     for (int i : all) {
         const AxisPlan &ax = plans[i]->host.ax[axis];
         const int K = ax.nst == 1 ? 1 : ax.R[ax.nst - 1];
-        const int gz = mode == pspfft::Z_CONV ? plans[i]->host.gz : 0;
+        const int gz = mode == pspfft::Z_CONV && plans[i]->host.gz ? ax.nst : 0;
         groups[{static_cast<int>(plans[i]->prec), ax.E, K, gz}].push_back(i);
     }
     for (auto &kv : groups) {
@@ -518,7 +529,8 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
             int block = 0, nbmax = 1;
             for (size_t j = c0; j < c1; ++j) nbmax = std::max(nbmax, plans[idx[j]]->host.ax[axis].NB);
             // (a kz-fastest spectrum needs the compile-time tile: no override)
-            const int tile_target = gz ? pspfft::fix_tile(prec, mode, nbmax)
+            const int gst = gz ? plans[idx[c0]]->host.ax[axis].nst : 0;
+            const int tile_target = gz ? pspfft::wave_tile(prec, mode, E, nbmax, gst)
                                        : line_tile(mode, pspfft::pass_tile(prec, mode, E, nbmax));
             for (size_t j = c0; j < c1; ++j) block = std::max(block, tile_target * plans[idx[j]]->host.ax[axis].NB);
             block = std::min(std::max(block, 64), bmax);
@@ -589,7 +601,7 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
                 else if (a0.nst == 4 && a0.R[1] == M && a0.R[2] == M && M < E && E * M * M * K <= 4096) fix = 4;
                 const int cnb = pspfft::fix_nb(fix, E, K);
                 if (fix && !gz && block != pspfft::pass_tile(prec, mode, E, cnb) * cnb) fix = 0;
-                if (fix && gz && block != pspfft::fix_tile(prec, mode, cnb) * cnb) fix = 0;
+                if (fix && gz && block != pspfft::wave_tile(prec, mode, E, cnb, fix) * cnb) fix = 0;
                 if (fix >= 3 && pspfft::pass_tile(prec, pspfft::Y_FWD, E, cnb) * cnb > pspfft::max_block_for(prec, E))
                     fix = 0;
                 bool wide = false;
@@ -600,7 +612,8 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
                 }
                 if (fix && wide) fix += pspfft::kFixWide;
             }
-            if (gz && fix != 3) return PSPFFT_ERR_UNSUPPORTED_SIZE;  // only wave_col_kernel reads that layout
+            // only wave_col_kernel reads that layout
+            if (gz && (fix & 7) != 3 && (fix & 7) != 4) return PSPFFT_ERR_UNSUPPORTED_SIZE;
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "
                           "threads, %zu B LDS", mode, prec, E, K, fix, args.count, args.nseg, wg, block, lds);
             if (pspfft::launch_pass(mode, prec, E, K, fix, args, grid, block, lds, stream) != hipSuccess)

@@ -52,12 +52,19 @@ def gpu_solve(n, h, S, dtype):
 
 # z sizes whose three-stage z lines are kept within one wavefront (spectrum kz-fastest)
 WAVE_Z = (256, 288, 384, 512)
+# z sizes whose four-stage FP32 z lines are kept within one wavefront (arrays below 4 GB):
+# 2nz = 1152 and 2304 (36*4*4*2, 36*4*4*4), 640 and 1280 (20*4*4*2, 20*4*4*4)
+WAVE_Z4 = (576, 1152, 320, 640)
+
+
+def kz_fastest_expected(nz, dtype):
+    return nz in WAVE_Z or (dtype == torch.float32 and nz in WAVE_Z4)
 
 
 # (16, 8, 512): z lines of 1024 = 16*16*4, kept kz-fastest
 @pytest.mark.parametrize("n,h", [((16, 16, 16), (1 / 16,) * 3), ((24, 10, 16), (0.3, 0.2, 0.5)),
                                  ((24, 18, 20), (0.05, 0.07, 0.06)), ((36, 8, 40), (1.0, 1.0, 2.0)),
-                                 ((16, 8, 512), (0.02, 0.03, 0.025))])
+                                 ((16, 8, 512), (0.02, 0.03, 0.025)), ((16, 8, 576), (0.02, 0.03, 0.025))])
 def test_green_spectrum_matches_oracle(n, h):
     from paper_1106_0557_amd import Plan
 
@@ -65,7 +72,7 @@ def test_green_spectrum_matches_oracle(n, h):
     want, imag_max, abs_max = oracle.green_hat_octant(n, h)
     for dtype, tol in ((torch.float64, FP64_TOL), (torch.float32, 1e-7)):
         plan = Plan(*n, h=h, dtype=dtype)
-        assert plan.spectrum_kz_fastest == (n[2] in WAVE_Z)
+        assert plan.spectrum_kz_fastest == kz_fastest_expected(n[2], dtype)
         got = plan.green().double().cpu().numpy()
         plan.close()
         err = np.abs(got - want).max() / abs_max
@@ -248,16 +255,27 @@ def test_long_lines_match_oracle(n):
 
 
 # Lines of four stages (radices E, M, M, K) with compile-time geometry: z lines
-# of 1152 (36*4*4*2), 2304 (36*4*4*4), 640 (20*4*4*2) and 3072 (24*8*8*2, FP32
-# only: FP64 meshes stop at 1152), y lines of 1152 and 1280 (20*4*4*4), x rows of
-# 1152 and 640.
-FOUR_STAGE = [(16, 8, 576), (16, 8, 1152), (16, 8, 320), (16, 8, 1536), (16, 576, 8), (16, 640, 8), (1152, 8, 8),
-              (640, 8, 8)]
+# of 1152 (36*4*4*2), 2304 (36*4*4*4), 640 (20*4*4*2), 1280 (20*4*4*4) and 3072
+# (24*8*8*2, FP32 only: FP64 meshes stop at 1152), y lines of 1152 and 1280, x
+# rows of 1152 and 640.  In FP32 the z lines of 1152, 2304, 640 and 1280 points
+# (and the y lines of 1152 and 1280) are kept within one wavefront; (20, 18, 576)
+# ends on partial tiles, and (80, 18, 576) and (40, 18, 1152) give the
+# persistent z workgroups several tiles each.
+FOUR_STAGE = [(16, 8, 576), (16, 8, 1152), (16, 8, 320), (16, 8, 640), (16, 8, 1536), (16, 576, 8), (16, 640, 8),
+              (1152, 8, 8), (640, 8, 8), (20, 18, 576), (80, 18, 576), (40, 18, 1152)]
 
 
 @pytest.mark.parametrize("n", FOUR_STAGE)
 def test_four_stage_lines_match_oracle(n):
     say(f"[four-stage] n={n}")
+    from paper_1106_0557_amd import Plan
+
+    for dt in (torch.float32, torch.float64):
+        if dt == torch.float64 and max(n) > 1152:
+            continue
+        p = Plan(*n, h=0.1, dtype=dt)
+        assert p.spectrum_kz_fastest == kz_fastest_expected(n[2], dt)
+        p.close()
     h = (0.02, 0.03, 0.025)
     S = sources.random_field(n, seed=sum(n) + 7).numpy()
     ref = oracle.solve_fft(S, h)
@@ -394,6 +412,8 @@ def test_config5_n512_sampled_direct_sum(dtype):
     n, h, S, targets, want = _config5_direct()
     assert targets.size == 256
     plan = Plan(n, n, n, h=h, dtype=dtype)
+    # z lines of 1024 within one wavefront (FP64: the 64-bit form, its workspace passes 4 GB)
+    assert plan.spectrum_kz_fastest
     phi = plan.solve(S.to("cuda", dtype))
     torch.cuda.synchronize()
     got = phi.reshape(-1)[torch.from_numpy(targets).cuda()].double().cpu().numpy()
@@ -441,6 +461,7 @@ def test_fp32_arrays_above_4gb_sampled_direct_sum():
     targets = np.concatenate([np.unique(rng.integers(0, size, size=24)), [0, size - 1, size // 2 + n[0] // 2]])
     want = oracle.direct(S.numpy(), h, targets)
     plan = Plan(*n, h=h, dtype=torch.float32)
+    assert plan.spectrum_kz_fastest  # z lines of 1024 within one wavefront, 64-bit block bases
     phi = plan.solve(S.to("cuda", torch.float32))
     torch.cuda.synchronize()
     got = phi.reshape(-1)[torch.from_numpy(targets).cuda()].double().cpu().numpy()
