@@ -193,13 +193,12 @@ __host__ __device__ constexpr int pass_tile(int prec, int mode, int E, int nb) {
 }
 
 // Lines per workgroup of the wavefront-owned column kernel for lines of NB
-// threads, ST compile-time stages: three-stage lines take the default tile;
-// four-stage ones (1152 and 2304 points in the 36-family, 640 and 1280 in the
-// 20-family; FP32) halve it while the workgroup exceeds the family's largest or
-// the tile's rows and the stage twiddles exceed the LDS.
+// threads, ST compile-time stages: the default tile, halved while the
+// workgroup exceeds the family's largest or the tile's rows and the stage
+// twiddles exceed the LDS (lines of 1536 points in the 24-family; four-stage
+// lines: 1152 and 2304 points in the 36-family, 640 and 1280 in the 20-family).
 __host__ __device__ constexpr int wave_tile(int prec, int mode, int E, int NB, int ST = 3) {
     int t = fix_tile(prec, mode, NB);
-    if (ST != 4) return t;
     const long L = static_cast<long>(E) * NB, csz = prec == 0 ? 8 : 16;
     while (t > 1 && (static_cast<long>(t) * NB > max_block_for(prec, E) ||
                      (t * static_cast<long>(wave_line_stride(static_cast<int>(L))) + L - 1) * csz > 160 * 1024))

@@ -1243,8 +1243,8 @@ hipError_t launch_kernel(const LaunchArgs &args, int grid, int block, size_t lds
 }
 
 // The wavefront-owned column kernel exists for three-stage lines of 16, 32 or 64
-// threads whose default tile fits the family's largest workgroup and the LDS,
-// and for four-stage FP32 lines of 32 or 64 threads (wave_tile() lines).
+// threads and four-stage FP32 lines of 32 or 64 threads whose tile of
+// wave_tile() lines fits the family's largest workgroup and the LDS.
 template <typename T, int E, int K, int MODE, int ST = 3>
 constexpr bool wave_col_fits() {
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
@@ -1256,14 +1256,14 @@ constexpr bool wave_col_fits() {
                wave_lds_bytes(prec, MODE, E, NB, 4) <= 160 * 1024;
     } else {
         constexpr int NB = M * K;
-        return (NB == 16 || NB == 32 || NB == 64) && fix_tile(prec, MODE, NB) * NB <= max_block_for(prec, E) &&
+        return (NB == 16 || NB == 32 || NB == 64) && wave_tile(prec, MODE, E, NB) * NB <= max_block_for(prec, E) &&
                wave_lds_bytes(prec, MODE, E, NB) <= 160 * 1024;
     }
 }
 
-// The y passes take the wavefront-owned kernel for three-stage lines where its
-// tile equals the column kernel's (pass_tile), from which the host counted the
-// launch's tiles.  Measured on 1152-point lines (576^3 FP32), four-stage y
+// The y passes take the wavefront-owned kernel for three-stage lines whose
+// default tile fits the family's largest workgroup, where its tile equals the
+// column kernel's (pass_tile), from which the host counted the launch's tiles.  Measured on 1152-point lines (576^3 FP32), four-stage y
 // lines lose 9 % in the forward pass and gain nothing in the inverse one.
 template <typename T, int E, int K, int MODE, int ST>
 constexpr bool wave_y_fits() {
@@ -1271,6 +1271,7 @@ constexpr bool wave_y_fits() {
     constexpr int M = E & -E;
     constexpr int NB = (ST == 4 ? M * M : M) * K;
     return ST == 3 && (NB == 32 || NB == 64) && wave_col_fits<T, E, K, MODE, ST>() &&
+           fix_tile(prec, MODE, NB) * NB <= max_block_for(prec, E) &&
            wave_tile(prec, MODE, E, NB, ST) == pass_tile(prec, MODE, E, NB);
 }
 

@@ -392,8 +392,9 @@ bool z_wave_lines(pspfft_plan_t p) {
                pspfft::wave_lds_bytes(prec, pspfft::Z_CONV, az.E, NB, 4) <= 160 * 1024;
     const bool nb_ok = NB == 32 || NB == 64 || (NB == 16 && pspfft::wave_z_lds_bytes(prec, az.E, NB) > 80 * 1024);
     return az.nst == 3 && az.R[1] == M && nb_ok && M * az.R[2] == NB &&
-           pspfft::fix_tile(prec, pspfft::Z_CONV, NB) * NB <= pspfft::max_block_for(prec, az.E) &&
-           pspfft::fix_tile(prec, pspfft::Y_FWD, NB) * NB <= pspfft::max_block_for(prec, az.E);
+           pspfft::wave_tile(prec, pspfft::Z_CONV, az.E, NB) * NB <= pspfft::max_block_for(prec, az.E) &&
+           pspfft::wave_lds_bytes(prec, pspfft::Z_CONV, az.E, NB) <= 160 * 1024 &&
+           pspfft::pass_tile(prec, pspfft::Y_FWD, az.E, NB) * NB <= pspfft::max_block_for(prec, az.E);
 }
 
 // Lines (main, Nyquist) that a pass processes for one problem.

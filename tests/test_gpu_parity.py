@@ -50,8 +50,9 @@ def gpu_solve(n, h, S, dtype):
 
 # ---------------------------------------------------------------- spectrum --
 
-# z sizes whose three-stage z lines are kept within one wavefront (spectrum kz-fastest)
-WAVE_Z = (256, 288, 384, 512)
+# z sizes whose three-stage z lines are kept within one wavefront (spectrum kz-fastest);
+# lines of 1536 (24*8*8) take a smaller tile
+WAVE_Z = (256, 288, 384, 512, 768)
 # z sizes whose four-stage FP32 z lines are kept within one wavefront (arrays below 4 GB):
 # 2nz = 1152 and 2304 (36*4*4*2, 36*4*4*4), 640 and 1280 (20*4*4*2, 20*4*4*4)
 WAVE_Z4 = (576, 1152, 320, 640)
@@ -243,6 +244,12 @@ LONG_LINES = [(16, 768, 8), (16, 8, 768), (768, 8, 8), (16, 1024, 8), (16, 8, 10
 @pytest.mark.parametrize("n", LONG_LINES)
 def test_long_lines_match_oracle(n):
     say(f"[long lines] n={n}")
+    from paper_1106_0557_amd import Plan
+
+    for dt in (torch.float32, torch.float64):
+        p = Plan(*n, h=0.1, dtype=dt)
+        assert p.spectrum_kz_fastest == kz_fastest_expected(n[2], dt)
+        p.close()
     h = (0.02, 0.03, 0.025)
     S = sources.random_field(n, seed=sum(n) + 3).numpy()
     ref = oracle.solve_fft(S, h)
