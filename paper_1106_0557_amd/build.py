@@ -22,7 +22,8 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-parameter", "-fno-signed-zeros",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-DEVICE_SOURCES = ["green.hip", "line_generic.hip", "noalloc.hip"] + [f"pass_{p}_e{e}.hip" for p in ("f32", "f64") for e in (16, 20, 24, 36)]
+DEVICE_SOURCES = (["green.hip", "line_generic.hip", "noalloc.hip", "pass_f32_e32.hip"]
+                  + [f"pass_{p}_e{e}.hip" for p in ("f32", "f64") for e in (16, 20, 24, 36)])
 HOST_SOURCES = ["pspfft_runtime.cpp"]
 
 

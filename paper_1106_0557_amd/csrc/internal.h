@@ -159,7 +159,7 @@ __host__ __device__ constexpr int fix_tile(int prec, int mode, int /*nb*/) {
 }
 
 __host__ __device__ constexpr int max_block_for(int prec, int E) {
-    return prec == 0 ? (E == 16 ? 1024 : (E <= 24 ? 512 : 256)) : (E == 16 ? 512 : 256);
+    return prec == 0 ? (E == 16 ? 1024 : (E <= 24 || E == 32 ? 512 : 256)) : (E == 16 ? 512 : 256);
 }
 
 // Line forms of the line-pass instances (template parameter FIX): FIX & 7 is
@@ -190,6 +190,12 @@ __host__ __device__ constexpr int pass_tile(int prec, int mode, int E, int nb) {
         t /= 2;
     }
     return t;
+}
+
+// Threads per line of the wavefront-owned column kernel: ST compile-time stages
+// with radices E, M, K (ST = 3) or E, M, M, K (4), M = E & -E.
+__host__ __device__ constexpr int wave_nb(int E, int K, int ST) {
+    return ST == 4 ? (E & -E) * (E & -E) * K : (E & -E) * K;
 }
 
 // Lines per workgroup of the wavefront-owned column kernel for lines of NB
@@ -271,6 +277,10 @@ PSPFFT_DECLARE_FAMILY(launch_f64_e20, plane_f64_e20)
 PSPFFT_DECLARE_FAMILY(launch_f64_e24, plane_f64_e24)
 PSPFFT_DECLARE_FAMILY(launch_f64_e36, plane_f64_e36)
 #undef PSPFFT_DECLARE_FAMILY
+// Radix family E = 32 (FP32): z lines of 2048 points (32*32*2) kept within one
+// wavefront; its launcher takes only those z passes.
+hipError_t launch_f32_e32(int mode, int K, int fix, const LaunchArgs &args, int grid, int block, size_t lds,
+                          hipStream_t stream);
 
 inline hipError_t launch_pass(int mode, int prec, int E, int K, int fix, const LaunchArgs &args, int grid,
                               int block, size_t lds, hipStream_t stream) {
@@ -280,6 +290,7 @@ inline hipError_t launch_pass(int mode, int prec, int E, int K, int fix, const L
         case 20: return launch_f32_e20(mode, K, fix, args, grid, block, lds, stream);
         case 24: return launch_f32_e24(mode, K, fix, args, grid, block, lds, stream);
         case 36: return launch_f32_e36(mode, K, fix, args, grid, block, lds, stream);
+        case 32: return launch_f32_e32(mode, K, fix, args, grid, block, lds, stream);
         case 116: return launch_f64_e16(mode, K, fix, args, grid, block, lds, stream);
         case 120: return launch_f64_e20(mode, K, fix, args, grid, block, lds, stream);
         case 124: return launch_f64_e24(mode, K, fix, args, grid, block, lds, stream);

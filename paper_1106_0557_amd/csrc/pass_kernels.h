@@ -778,7 +778,7 @@ __device__ __forceinline__ ZLine<T> y_line(const LaunchArgs &args, int bid, int 
 
 // Column passes (Y_FWD, Z_CONV, Y_INV) for lines of 16, 32 or 64 threads
 // (ST = 3: radices E, M, K with M*K = NB; ST = 4: E, M, M, K with M*M*K = NB,
-// FP32 only, and a tile of wave_tile() lines): each line lies within one wavefront
+// FP32 only; a tile of wave_tile() lines): each line lies within one wavefront
 // (wavefront w holds lines w*64/NB onwards), so the stage exchanges stay inside
 // the wavefront and need no workgroup barrier.  The tile's stored half (all of
 // it for Y_INV) is loaded with adjacent lanes on adjacent lines (128-byte row
@@ -801,7 +801,7 @@ __device__ __forceinline__ ZLine<T> y_line(const LaunchArgs &args, int bid, int 
 template <typename T, int E, int K, int MODE, bool PERSIST, int ST = 3, bool WIDE = false>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E)))
 __attribute__((amdgpu_waves_per_eu(wave_waves_per_simd(sizeof(T) == 4 ? 0 : 1, MODE, E,
-                                                       (ST == 4 ? (E & -E) * (E & -E) : (E & -E)) * K, ST))))
+                                                       wave_nb(E, K, ST), ST))))
 wave_col_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
@@ -809,7 +809,7 @@ wave_col_kernel(const LaunchArgs args) {
     static_assert(ST == 3 || (ST == 4 && sizeof(T) == 4), "three-stage lines, or four-stage ones in FP32");
     static_assert(!WIDE || MODE == Z_CONV, "64-bit bases for z lines only");
     constexpr int H = E / 2;
-    constexpr int NB = (ST == 4 ? (E & -E) * (E & -E) : (E & -E)) * K;
+    constexpr int NB = wave_nb(E, K, ST);
     static_assert(NB == 16 || NB == 32 || NB == 64, "lines of 16, 32 or 64 threads");
     constexpr int L = E * NB;
     constexpr int TILE = wave_tile(sizeof(T) == 4 ? 0 : 1, MODE, E, NB, ST);
@@ -1163,7 +1163,7 @@ template <typename T, int E, int K, int MODE, int ST = 3, bool WIDE = false>
 hipError_t launch_wave_col(const LaunchArgs &args, hipStream_t stream) {
     constexpr int kMaxDevices = 64;
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
-    constexpr int NB = (ST == 4 ? (E & -E) * (E & -E) : (E & -E)) * K;
+    constexpr int NB = wave_nb(E, K, ST);
     constexpr int block = wave_tile(prec, MODE, E, NB, ST) * NB;
     constexpr size_t lds = wave_lds_bytes(prec, MODE, E, NB, ST);
     static_assert(lds <= 160 * 1024, "tile rows and twiddles fit the LDS");
@@ -1250,10 +1250,10 @@ constexpr bool wave_col_fits() {
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
     constexpr int M = E & -E;
     if constexpr (ST == 4) {
-        constexpr int NB = M * M * K;
+        constexpr int NB = wave_nb(E, K, ST);
         return prec == 0 && M < E && (NB == 32 || NB == 64) &&
-               wave_tile(prec, MODE, E, NB, 4) * NB <= max_block_for(prec, E) &&
-               wave_lds_bytes(prec, MODE, E, NB, 4) <= 160 * 1024;
+               wave_tile(prec, MODE, E, NB, ST) * NB <= max_block_for(prec, E) &&
+               wave_lds_bytes(prec, MODE, E, NB, ST) <= 160 * 1024;
     } else {
         constexpr int NB = M * K;
         return (NB == 16 || NB == 32 || NB == 64) && wave_tile(prec, MODE, E, NB) * NB <= max_block_for(prec, E) &&
@@ -1269,7 +1269,7 @@ template <typename T, int E, int K, int MODE, int ST>
 constexpr bool wave_y_fits() {
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
     constexpr int M = E & -E;
-    constexpr int NB = (ST == 4 ? M * M : M) * K;
+    constexpr int NB = wave_nb(E, K, ST);
     return ST == 3 && (NB == 32 || NB == 64) && wave_col_fits<T, E, K, MODE, ST>() &&
            fix_tile(prec, MODE, NB) * NB <= max_block_for(prec, E) &&
            wave_tile(prec, MODE, E, NB, ST) == pass_tile(prec, MODE, E, NB);

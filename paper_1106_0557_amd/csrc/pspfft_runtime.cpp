@@ -136,6 +136,21 @@ int xcd_remap_mode(int mode) {
     return (mode >= 0 && mode < 5) ? modes[mode] : 0;
 }
 
+// FP32 z lines of 2048 points on the 32-family (radices 32, 32, 2: 64 threads
+// per line, so the line fits one wavefront; PSPFFT_Z32=0 keeps the 16-family's
+// 16, 16, 8, 128 threads per line).  Measured, one 1024^3 solve: z pass 24.4 ->
+// 18.2 ms.  Lines of 1024 points stay on the 16-family: as 32 x 32 (two lines
+// per wavefront, eight wavefronts per CU instead of sixteen) the 512^3 z pass
+// takes 1.56 ms instead of 1.43.
+bool z32_enabled() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = std::getenv("PSPFFT_Z32");
+        v = e && std::atoi(e) == 0 ? 0 : 1;
+    }
+    return v == 1;
+}
+
 // Lines per workgroup of each pass; PSPFFT_TILE="a,b,c,d,e" overrides (powers of two).
 int line_tile(int mode, int dflt) {
     static int v[5] = {-1, -1, -1, -1, -1};
@@ -248,9 +263,11 @@ std::vector<int> generic_radices(int L) {
 // Stage plan and FP64 twiddles of one axis: a radix family's stages (every
 // radix divides E) where the family kernels take the length, else the generic
 // kernel's radices.
-bool build_axis(int axis, int n, pspfft_precision prec, AxisPlan &ax, std::vector<std::complex<double>> &tw) {
+bool build_axis(int axis, int n, pspfft_precision prec, AxisPlan &ax, std::vector<std::complex<double>> &tw,
+                int force_E = 0) {
     const int L = axis_len(axis, n);
-    const int E = family_axis(axis, n, prec) ? family_of_len(L) : 0;
+    const int E = force_E ? force_E : (family_axis(axis, n, prec) ? family_of_len(L) : 0);
+    if (force_E && L % force_E != 0) return false;
     if (!E && !(n <= kGenericMaxN && smooth235(n))) return false;
     std::memset(&ax, 0, sizeof(ax));
     ax.n = n;
@@ -793,6 +810,15 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
         if (!build_axis(a, p->n[a], prec, p->host.ax[a], tws[a]))
             return fail(PSPFFT_ERR_UNSUPPORTED_SIZE, vlevel, "%s: no stage plan for axis %d (n = %d)", who, a,
                         p->n[a]);
+        if (a == 2 && z32_enabled() && prec == PSPFFT_FP32 && p->host.ax[2].E == 16 && p->host.ax[2].L == 2048) {
+            // the 32-family's z lines, where the wavefront-owned z kernel takes them
+            const AxisPlan keep = p->host.ax[2];
+            std::vector<std::complex<double>> tw32;
+            if (build_axis(2, p->n[2], prec, p->host.ax[2], tw32, 32) && z_wave_lines(p))
+                tws[2].swap(tw32);
+            else
+                p->host.ax[2] = keep;
+        }
         const AxisPlan &ax = p->host.ax[a];
         char radices[96] = {0};
         for (int s2 = 0, off = 0; s2 < ax.nst && off < 90; ++s2)

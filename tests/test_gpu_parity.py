@@ -58,8 +58,12 @@ WAVE_Z = (256, 288, 384, 512, 768)
 WAVE_Z4 = (576, 1152, 320, 640)
 
 
+# z sizes whose FP32 z lines go to the 32-family, within one wavefront: 2048 = 32*32*2
+WAVE_Z32 = (1024,)
+
+
 def kz_fastest_expected(nz, dtype):
-    return nz in WAVE_Z or (dtype == torch.float32 and nz in WAVE_Z4)
+    return nz in WAVE_Z or (dtype == torch.float32 and (nz in WAVE_Z4 or nz in WAVE_Z32))
 
 
 # (16, 8, 512): z lines of 1024 = 16*16*4, kept kz-fastest
@@ -237,8 +241,11 @@ def test_three_stage_lines_match_oracle(n):
 # 768) and (40, 18, 1024) give z workgroups several tiles each (more tiles than
 # CUs) and a partial last Nyquist tile (36 lines), whose spare lanes repeat the
 # set's last line, and (80, 768, 36) does the same for the y passes.
+# FP32 z lines of 2048 points go to the 32-family (32*32*2, within one wavefront):
+# (48, 36, 1024) gives its persistent workgroups several tiles; (80, 36, 512) does the
+# same for the 16-family's 1024-point lines.
 LONG_LINES = [(16, 768, 8), (16, 8, 768), (768, 8, 8), (16, 1024, 8), (16, 8, 1024), (1024, 8, 8), (2048, 8, 8),
-              (80, 18, 768), (40, 18, 1024), (80, 768, 36)]
+              (80, 18, 768), (40, 18, 1024), (80, 768, 36), (80, 36, 512), (48, 36, 1024)]
 
 
 @pytest.mark.parametrize("n", LONG_LINES)

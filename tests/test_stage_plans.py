@@ -3,7 +3,8 @@ pspfft_plan_create_ex prints before any device work (no GPU needed).
 
 Every length 2^a 3^b 5^c gets a plan whose radices multiply to the line length:
 the radix families (odd part 1, 3, 5, 9) split a doubled line of 2n points into
-stages that all divide the family's element count; the generic kernel takes the
+stages that all divide the family's element count (FP32 z lines of 2048 points
+take the 32-family); the generic kernel takes the
 largest of its radices that divides what is left (Sec. 2.2.2: the 1D transforms
 of every axis; the stage plan is this implementation's)."""
 import ctypes
@@ -78,3 +79,10 @@ def test_family_and_generic_stage_choices():
     assert p["z"] == (1536, 3072, [16, 16, 12], False)
     p = _plans((16, 2048, 1536), prec=0)
     assert p["y"][3] and p["z"][3]                       # FP32: families up to 2048
+    # FP32 z lines of 2048 points: the 32-family (lines within one wavefront)
+    assert _plans((16, 8, 512))["z"] == (512, 1024, [16, 16, 4], True)
+    assert _plans((16, 8, 1024))["z"] == (1024, 2048, [32, 32, 2], True)
+    assert _plans((16, 8, 512), prec=1)["z"] == (512, 1024, [16, 16, 4], True)
+    assert _plans((16, 512, 8))["y"] == (512, 1024, [16, 16, 4], True)  # y lines keep the 16-family
+    # unless a z line's block of 64 positions (64 * 2ny * nx values) reaches 4 GB
+    assert _plans((2048, 2048, 1024))["z"] == (1024, 2048, [16, 16, 8], True)
