@@ -1261,17 +1261,20 @@ constexpr bool wave_col_fits() {
     }
 }
 
-// The y passes take the wavefront-owned kernel for three-stage lines whose
-// default tile fits the family's largest workgroup, where its tile equals the
-// column kernel's (pass_tile), from which the host counted the launch's tiles.  Measured on 1152-point lines (576^3 FP32), four-stage y
-// lines lose 9 % in the forward pass and gain nothing in the inverse one.
+// The y passes take the wavefront-owned kernel where its tile equals the
+// column kernel's (pass_tile), from which the host counted the launch's tiles:
+// three-stage lines whose default tile fits the family's largest workgroup,
+// and four-stage lines where the kernel runs two workgroups per CU (twiddles
+// in global memory: the 36-family).  Measured, 576^3 FP32 (1152-point lines):
+// y passes 1.53 / 1.77 -> 1.47 / 1.56 ms; with one workgroup per CU (the
+// 20-family's 640-point lines of 320^3) 0.176 / 0.199 -> 0.215 / 0.213 ms.
 template <typename T, int E, int K, int MODE, int ST>
 constexpr bool wave_y_fits() {
     constexpr int prec = sizeof(T) == 4 ? 0 : 1;
-    constexpr int M = E & -E;
     constexpr int NB = wave_nb(E, K, ST);
-    return ST == 3 && (NB == 32 || NB == 64) && wave_col_fits<T, E, K, MODE, ST>() &&
-           fix_tile(prec, MODE, NB) * NB <= max_block_for(prec, E) &&
+    return (NB == 32 || NB == 64) && wave_col_fits<T, E, K, MODE, ST>() &&
+           ((ST == 3 && fix_tile(prec, MODE, NB) * NB <= max_block_for(prec, E)) ||
+            (ST == 4 && !wave_tw_lds(prec, MODE, E, NB, ST))) &&
            wave_tile(prec, MODE, E, NB, ST) == pass_tile(prec, MODE, E, NB);
 }
 
