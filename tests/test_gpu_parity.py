@@ -459,13 +459,15 @@ def test_config5_fp64_and_fp32_agree_on_every_cell():
     assert d <= FP32_TOL
 
 
-def test_fp32_arrays_above_4gb_sampled_direct_sum():
-    """An FP32 mesh whose workspace passes 4 GB (64-bit addressing), with x rows of
-    768 = 24*8*4, y lines of 1536 = 24*8*8 and z lines of 1024 = 16*16*4, checked
-    at sampled targets by the direct sum."""
+# FP32 meshes whose workspace passes 4 GB (64-bit addressing): x rows of 768 = 24*8*4,
+# y lines of 1536 = 24*8*8 and z lines of 1024 = 16*16*4; then y lines of 1152 =
+# 36*4*4*2 and z lines of 1280 = 20*4*4*4, the z lines kept within one wavefront
+# (64-bit bases per block of positions).
+@pytest.mark.parametrize("n", [(768, 768, 512), (768, 576, 640)])
+def test_fp32_arrays_above_4gb_sampled_direct_sum(n):
+    """An FP32 mesh whose workspace passes 4 GB, checked at sampled targets by the direct sum."""
     from paper_1106_0557_amd import Plan, workspace_bytes
 
-    n = (768, 768, 512)
     h = (0.011, 0.009, 0.013)
     say(f"[above_4gb] n={n} fp32")
     assert workspace_bytes(*n, torch.float32) >= 1 << 32
@@ -475,7 +477,7 @@ def test_fp32_arrays_above_4gb_sampled_direct_sum():
     targets = np.concatenate([np.unique(rng.integers(0, size, size=24)), [0, size - 1, size // 2 + n[0] // 2]])
     want = oracle.direct(S.numpy(), h, targets)
     plan = Plan(*n, h=h, dtype=torch.float32)
-    assert plan.spectrum_kz_fastest  # z lines of 1024 within one wavefront, 64-bit block bases
+    assert plan.spectrum_kz_fastest  # z lines within one wavefront, 64-bit block bases
     phi = plan.solve(S.to("cuda", torch.float32))
     torch.cuda.synchronize()
     got = phi.reshape(-1)[torch.from_numpy(targets).cuda()].double().cpu().numpy()
