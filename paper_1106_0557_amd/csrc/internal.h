@@ -192,6 +192,17 @@ __host__ __device__ constexpr int pass_tile(int prec, int mode, int E, int nb) {
     return t;
 }
 
+// Row passes (X_FWD, X_INV) of compile-time lines of NB threads keep their
+// stage twiddles and split factors in global memory (a table the L1 holds)
+// where their pass_tile() rows alone let two workgroups share a CU and rows
+// plus those 2L - 1 values let only one.
+__host__ __device__ constexpr bool row_tables_global(int prec, int E, int NB) {
+    const int L = E * NB, csz = prec == 0 ? 8 : 16;
+    const long cap = 160 * 1024;
+    const long data = static_cast<long>(data_elems(true, L, NB, pass_tile(prec, X_FWD, E, NB) * NB, csz)) * csz;
+    return cap / data >= 2 && cap / (data + static_cast<long>(2 * L - 1) * csz) == 1;
+}
+
 // Threads per line of the wavefront-owned column kernel: ST compile-time stages
 // with radices E, M, K (ST = 3) or E, M, M, K (4), M = E & -E.
 __host__ __device__ constexpr int wave_nb(int E, int K, int ST) {

@@ -369,8 +369,15 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         t = tid >> __builtin_ctz(tile);
     }
     const int ldsw = ST ? CLDSW : (ROW ? row_stride(L, NB, CSZ) : col_stride(L, tile, CSZ));
-    cx<T> *twl = lds + (ST ? data_elems(ROW, CL, CNB, FTILE * CNB, CSZ) : data_elems(ROW, L, NB, block, CSZ));
-    copy_to_lds<T>(twl, ax.tw, ax.ntw);
+    // GT: compile-time rows whose stage twiddles and split factors stay in
+    // global memory (row_tables_global), else both follow the rows in LDS
+    constexpr bool GT = ROW && ST != 0 && row_tables_global(sizeof(T) == 4 ? 0 : 1, E, CNB);
+    cx<T> *twd = lds + (ST ? data_elems(ROW, CL, CNB, FTILE * CNB, CSZ) : data_elems(ROW, L, NB, block, CSZ));
+    if constexpr (!GT) copy_to_lds<T>(twd, ax.tw, ax.ntw);
+    const auto twl = [&]() __attribute__((always_inline)) {
+        if constexpr (GT) return as_global(static_cast<const cx<T> *>(ax.tw));
+        else return static_cast<const cx<T> *>(twd);
+    }();
 
     const bool nyq = local >= sg.wg_main;
     if (nyq) local -= sg.wg_main;
@@ -383,8 +390,16 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     if constexpr (ROW) {
         // Rows (y, z), y < ny, z < nz; row r = z*ny + y.  Packed real transform of
         // length n: u[j] = s[2j] + i s[2j+1], zero for j >= n/2 (the padding).
-        cx<T> *post = twl + ax.ntw;  // exp(-i pi k / n), k < n
-        copy_to_lds<T>(post, ax.post, L);
+        // exp(-i pi k / n), k < n
+        const auto post = [&]() __attribute__((always_inline)) {
+            if constexpr (GT) {
+                return as_global(static_cast<const cx<T> *>(ax.post));
+            } else {
+                cx<T> *p = twd + ax.ntw;
+                copy_to_lds<T>(p, ax.post, L);
+                return static_cast<const cx<T> *>(p);
+            }
+        }();
         const int nrows = ny * nz;
         const bool active = g < nrows;
         const int z = active ? g / ny : 0;
@@ -437,7 +452,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                     const cx<T> w = wp[m];
                     const cx<T> a = {static_cast<T>(0.5) * (u.x + w.x), static_cast<T>(0.5) * (u.y - w.y)};
                     const cx<T> b = {static_cast<T>(0.5) * (u.x - w.x), static_cast<T>(0.5) * (u.y + w.y)};
-                    const cx<T> eb = cmul(post[k], b);
+                    const cx<T> eb = cmul(tw_at(post, k), b);
                     wl[m] = cx<T>{a.x + eb.y, a.y - eb.x};  // a - i e b
                     if (k == 0) *wnyq = cx<T>{u.x - u.y, T(0)};
                 }
@@ -479,7 +494,7 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
                 const cx<T> b = k == 0 ? xn : wp[m];
                 const cx<T> sm = {a.x + b.x, a.y - b.y};
                 const cx<T> df = {a.x - b.x, a.y + b.y};
-                const cx<T> ed = cmulc(df, post[k]);
+                const cx<T> ed = cmulc(df, tw_at(post, k));
                 v[m] = cx<T>{sm.x - ed.y, sm.y + ed.x};
             }
             // with the mirror lanes nothing of the row is in LDS yet: no leading barrier

@@ -566,7 +566,7 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
             };
             while (block > nbmax && lds_need(block) > 160 * 1024) block /= 2;
             if (block < nbmax || lds_need(block) > 160 * 1024) return PSPFFT_ERR_UNSUPPORTED_SIZE;
-            const size_t lds = lds_need(block);
+            size_t lds = lds_need(block);
             LaunchArgs args;
             std::memset(&args, 0, sizeof(args));
             args.count = static_cast<int>(c1 - c0);
@@ -632,6 +632,11 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
             }
             // only wave_col_kernel reads that layout
             if (gz && (fix & 7) != 3 && (fix & 7) != 4) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+            // compile-time rows that keep their tables in global memory need only their rows in LDS
+            if (fix && row && pspfft::row_tables_global(prec, E, pspfft::fix_nb(fix, E, K))) {
+                const AxisPlan &a0 = plans[idx[c0]]->host.ax[axis];
+                lds = static_cast<size_t>(pspfft::data_elems(true, a0.L, a0.NB, block, csz)) * csz;
+            }
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "
                           "threads, %zu B LDS", mode, prec, E, K, fix, args.count, args.nseg, wg, block, lds);
             if (pspfft::launch_pass(mode, prec, E, K, fix, args, grid, block, lds, stream) != hipSuccess)

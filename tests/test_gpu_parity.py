@@ -206,10 +206,11 @@ def test_solve_matches_oracle(n):
 # 512 (16*16*2), 1024 (16*16*4), 768 (24*8*4) and 576 (36*4*4), each kept within
 # one wavefront, 384 (24*8*2), 320 (20*4*4); y lines of 1024 (16*16*4) and 768
 # (24*8*4), each kept within one wavefront, 384 (24*8*2), 288 (36*4*2), 160
-# (20*4*2); x rows of 512 and 384.
+# (20*4*2); x rows of 512, 384 and 576 (36*4*4, stage tables in global memory; (576, 20, 18)
+# spans several row tiles with a partial last one).
 THREE_STAGE = [(16, 8, 256), (16, 8, 512), (16, 8, 384), (16, 8, 192), (16, 8, 288), (16, 512, 8),
                (16, 384, 8), (16, 192, 8), (16, 144, 8), (20, 80, 160), (512, 8, 8), (384, 8, 8),
-               (16, 384, 288)]
+               (16, 384, 288), (576, 8, 8), (576, 20, 18)]
 
 
 @pytest.mark.parametrize("n", THREE_STAGE)
