@@ -203,6 +203,27 @@ __host__ __device__ constexpr bool row_tables_global(int prec, int E, int NB) {
     return cap / data >= 2 && cap / (data + static_cast<long>(2 * L - 1) * csz) == 1;
 }
 
+// Column y passes (Y_FWD, Y_INV) of compile-time lines of NB threads keep their
+// stage twiddles in global memory and pack the tile's positions (LDS stride =
+// tile) where that lets two workgroups of pass_tile() lines share a CU and the
+// layout with the twiddles in LDS lets only one.  col_ldsw: the LDS position
+// stride of such a launch; col_default_lds: its bytes with the twiddles in LDS.
+__host__ __device__ constexpr size_t col_default_lds(int prec, int mode, int E, int NB) {
+    const int L = E * NB, csz = prec == 0 ? 8 : 16;
+    const int tile = pass_tile(prec, mode, E, NB);
+    return (static_cast<size_t>(L) * col_stride(L, tile, csz) + L - 1) * csz;
+}
+__host__ __device__ constexpr bool col_tables_global(int prec, int mode, int E, int NB) {
+    if (mode != Y_FWD && mode != Y_INV) return false;
+    const long L = static_cast<long>(E) * NB, csz = prec == 0 ? 8 : 16, cap = 160 * 1024;
+    const long packed = L * pass_tile(prec, mode, E, NB) * csz;
+    return cap / packed >= 2 && cap / static_cast<long>(col_default_lds(prec, mode, E, NB)) == 1;
+}
+__host__ __device__ constexpr int col_ldsw(int prec, int mode, int E, int NB) {
+    const int tile = pass_tile(prec, mode, E, NB);
+    return col_tables_global(prec, mode, E, NB) ? tile : col_stride(E * NB, tile, prec == 0 ? 8 : 16);
+}
+
 // Threads per line of the wavefront-owned column kernel: ST compile-time stages
 // with radices E, M, K (ST = 3) or E, M, M, K (4), M = E & -E.
 __host__ __device__ constexpr int wave_nb(int E, int K, int ST) {

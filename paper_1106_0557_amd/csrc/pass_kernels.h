@@ -322,7 +322,8 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     constexpr int CNB = fix_nb(FIX, E, K);
     constexpr int FTILE = pass_tile(sizeof(T) == 4 ? 0 : 1, MODE, E, CNB);
     constexpr int CL = E * CNB;  // line length when compile-time
-    constexpr int CLDSW = ST ? (ROW ? row_stride(CL, CNB, CSZ) : col_stride(CL, FTILE, CSZ)) : 0;
+    constexpr int PREC = sizeof(T) == 4 ? 0 : 1;
+    constexpr int CLDSW = ST ? (ROW ? row_stride(CL, CNB, CSZ) : col_ldsw(PREC, MODE, E, CNB)) : 0;
     using FFT_F = LineFFT<T, E, -1, ROW, CNB, CLDSW>;
     using FFT_I = LineFFT<T, E, +1, ROW, CNB, CLDSW>;
     // compile-time rows of at most 64 threads are consecutive lanes of one
@@ -370,9 +371,11 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
     }
     const int ldsw = ST ? CLDSW : (ROW ? row_stride(L, NB, CSZ) : col_stride(L, tile, CSZ));
     // GT: compile-time rows whose stage twiddles and split factors stay in
-    // global memory (row_tables_global), else both follow the rows in LDS
-    constexpr bool GT = ROW && ST != 0 && row_tables_global(sizeof(T) == 4 ? 0 : 1, E, CNB);
-    cx<T> *twd = lds + (ST ? data_elems(ROW, CL, CNB, FTILE * CNB, CSZ) : data_elems(ROW, L, NB, block, CSZ));
+    // global memory (row_tables_global), or column y lines whose twiddles do
+    // (col_tables_global, positions packed); else the tables follow the data in LDS
+    constexpr bool GT = ST != 0 && (ROW ? row_tables_global(PREC, E, CNB) : col_tables_global(PREC, MODE, E, CNB));
+    cx<T> *twd = lds + (ST ? (ROW ? data_elems(true, CL, CNB, FTILE * CNB, CSZ) : CL * CLDSW)
+                           : data_elems(ROW, L, NB, block, CSZ));
     if constexpr (!GT) copy_to_lds<T>(twd, ax.tw, ax.ntw);
     const auto twl = [&]() __attribute__((always_inline)) {
         if constexpr (GT) return as_global(static_cast<const cx<T> *>(ax.tw));
@@ -1052,7 +1055,8 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) co
     constexpr int NB = fix_nb(FIX, E, K);
     constexpr int TILE = pass_tile(prec, MODE, E, NB);
     constexpr int L = E * NB;
-    constexpr int LDSW = col_stride(L, TILE, CSZ);
+    constexpr int LDSW = col_ldsw(prec, MODE, E, NB);
+    constexpr bool GT = col_tables_global(prec, MODE, E, NB);  // twiddles in global memory
     using FFT_F = LineFFT<T, E, -1, false, NB, LDSW>;
     using FFT_I = LineFFT<T, E, +1, false, NB, LDSW>;
 
@@ -1063,8 +1067,15 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) co
     const int c = tid & (TILE - 1), t = tid >> __builtin_ctz(TILE);  // adjacent lanes on adjacent lines
     // every problem of the launch has lines of length L: the same stage twiddles
     const AxisPlan &ax0 = args.p[0].plan->ax[ZC ? 2 : 1];
-    cx<T> *twl = lds + data_elems(false, L, NB, TILE * NB, CSZ);
-    copy_to_lds<T>(twl, ax0.tw, ax0.ntw);  // published by the first transform's barrier
+    const auto twl = [&]() __attribute__((always_inline)) {
+        if constexpr (GT) {
+            return as_global(static_cast<const cx<T> *>(ax0.tw));
+        } else {
+            cx<T> *p = lds + L * LDSW;
+            copy_to_lds<T>(p, ax0.tw, ax0.ntw);  // published by the first transform's barrier
+            return static_cast<const cx<T> *>(p);
+        }
+    }();
 
     cx<T> ln[NLOAD];     // the loaded part of this thread's line
     T gn[ZC ? E : 1];    // z: spectrum values of its positions
@@ -1299,10 +1310,12 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
         case X_FWD: return launch_kernel<T, E, K, X_FWD, FIX>(args, grid, block, lds, stream);
         case Y_FWD:
             if constexpr (FIX == 3 && wave_y_fits<T, E, K, Y_FWD, 3>()) {
-                if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_FWD>(args, stream);
+                if (col_default_lds(sizeof(T) == 4 ? 0 : 1, Y_FWD, E, wave_nb(E, K, 3)) > wave_y_min_lds())
+                    return launch_wave_col<T, E, K, Y_FWD>(args, stream);
             }
             if constexpr (FIX == 4 && wave_y_fits<T, E, K, Y_FWD, 4>()) {
-                if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_FWD, 4>(args, stream);
+                if (col_default_lds(sizeof(T) == 4 ? 0 : 1, Y_FWD, E, wave_nb(E, K, 4)) > wave_y_min_lds())
+                    return launch_wave_col<T, E, K, Y_FWD, 4>(args, stream);
             }
             if constexpr (FIX != 0) return launch_col<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
             else return launch_kernel<T, E, K, Y_FWD, FIX>(args, grid, block, lds, stream);
@@ -1324,10 +1337,12 @@ hipError_t launch_mode(int mode, const LaunchArgs &args, int grid, int block, si
             else return launch_kernel<T, E, K, Z_CONV, FIX>(args, grid, block, lds, stream);
         case Y_INV:
             if constexpr (FIX == 3 && wave_y_fits<T, E, K, Y_INV, 3>()) {
-                if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_INV>(args, stream);
+                if (col_default_lds(sizeof(T) == 4 ? 0 : 1, Y_INV, E, wave_nb(E, K, 3)) > wave_y_min_lds())
+                    return launch_wave_col<T, E, K, Y_INV>(args, stream);
             }
             if constexpr (FIX == 4 && wave_y_fits<T, E, K, Y_INV, 4>()) {
-                if (lds > wave_y_min_lds()) return launch_wave_col<T, E, K, Y_INV, 4>(args, stream);
+                if (col_default_lds(sizeof(T) == 4 ? 0 : 1, Y_INV, E, wave_nb(E, K, 4)) > wave_y_min_lds())
+                    return launch_wave_col<T, E, K, Y_INV, 4>(args, stream);
             }
             if constexpr (FIX != 0) return launch_col<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);
             else return launch_kernel<T, E, K, Y_INV, FIX>(args, grid, block, lds, stream);

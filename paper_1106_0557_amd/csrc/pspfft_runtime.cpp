@@ -121,11 +121,15 @@ pspfft_status fail(pspfft_status st, int plan_level, const char *fmt, ...) {
 
 // Workgroup renumbering for the XCDs, per pass (0 none, 1 contiguous eighths,
 // 2 runs of 8 within blocks of 64).  PSPFFT_XCD_REMAP="abcde" overrides the
-// five passes in order.
+// five passes in order.  Measured: the row passes and the y passes gain from
+// contiguous eighths (y passes of one solve: FP64 768^3 8.0 / 8.9 -> 6.8 /
+// 7.0 ms, 256^3 0.156 / 0.160 -> 0.146 / 0.147 ms; FP32 1152^3, whose column
+// kernel keeps its twiddles in global memory, 32.7 / 21.3 -> 14.1 / 12.4 ms),
+// the z pass loses.
 int xcd_remap_mode(int mode) {
     static int modes[5] = {-1, -1, -1, -1, -1};
     if (modes[0] < 0) {
-        const int dflt[5] = {1, 0, 0, 0, 1};
+        const int dflt[5] = {1, 1, 0, 1, 1};
         const char *e = std::getenv("PSPFFT_XCD_REMAP");
         for (int i = 0; i < 5; ++i) {
             int v = dflt[i];
@@ -632,10 +636,15 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
             }
             // only wave_col_kernel reads that layout
             if (gz && (fix & 7) != 3 && (fix & 7) != 4) return PSPFFT_ERR_UNSUPPORTED_SIZE;
-            // compile-time rows that keep their tables in global memory need only their rows in LDS
+            // compile-time lines that keep their tables in global memory need only
+            // their rows (or packed column positions) in LDS
             if (fix && row && pspfft::row_tables_global(prec, E, pspfft::fix_nb(fix, E, K))) {
                 const AxisPlan &a0 = plans[idx[c0]]->host.ax[axis];
                 lds = static_cast<size_t>(pspfft::data_elems(true, a0.L, a0.NB, block, csz)) * csz;
+            }
+            if (fix && !row && !gz && pspfft::col_tables_global(prec, mode, E, pspfft::fix_nb(fix, E, K))) {
+                const AxisPlan &a0 = plans[idx[c0]]->host.ax[axis];
+                lds = static_cast<size_t>(a0.L) * (block / a0.NB) * csz;
             }
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "
                           "threads, %zu B LDS", mode, prec, E, K, fix, args.count, args.nseg, wg, block, lds);
