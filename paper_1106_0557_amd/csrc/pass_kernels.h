@@ -620,7 +620,9 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
 // sharing a spectrum slice) are then in flight on one XCD and meet in its L2,
 // while the XCDs together still sweep one narrow address window at a time.
 // Otherwise the walk is b, b + grid, ...  The tile index grows along a
-// workgroup's walk, so the first tile at or past the end ends it.
+// workgroup's walk, so the first tile at or past the end ends it.  A launch
+// whose workgroups take one tile each pads its grid to whole rounds of
+// 8 * kTileChunk workgroups, over which the chunked order is one to one.
 //
 // Measured on single solves: the chunked order takes the 1152^3 FP32 solve
 // from 139 to 114 ms (its forward y pass from 36 to 16 ms) and 576^3 / 768^3
@@ -838,7 +840,9 @@ wave_col_kernel(const LaunchArgs args) {
     using FFT_F = LineFFT<T, E, -1, true, NB, S>;
     using FFT_I = LineFFT<T, E, +1, true, NB, S>;
 
-    TileWalk walk = tile_walk<PERSIST && E != 16>();
+    // (one tile per workgroup: the launch pads its grid to a multiple of 64, so
+    // that the chunked order maps the workgroups onto the tiles one to one)
+    TileWalk walk = tile_walk<E != 16>();
     int bid = walk.tile();
     if (bid >= args.nwg) return;
     const int tid = threadIdx.x;
@@ -1220,7 +1224,10 @@ hipError_t launch_wave_col(const LaunchArgs &args, hipStream_t stream) {
         if (grid > args.nwg) grid = args.nwg;
         hipLaunchKernelGGL(fp, dim3(grid), dim3(block), lds, stream, args);
     } else {
-        hipLaunchKernelGGL(fo, dim3(args.nwg), dim3(block), lds, stream, args);
+        // chunked tile order (tile_walk): a grid of whole chunk rounds (8 XCDs x kTileChunk)
+        constexpr int round = E != 16 ? 8 * kTileChunk : 1;
+        const int grid = (args.nwg + round - 1) / round * round;
+        hipLaunchKernelGGL(fo, dim3(grid), dim3(block), lds, stream, args);
     }
     return hipGetLastError();
 }
