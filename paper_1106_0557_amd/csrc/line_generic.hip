@@ -111,19 +111,27 @@ __device__ cx<T> *gen_transform(cx<T> *a, cx<T> *b, const GenMap &m, int tile, c
     return a;
 }
 
-// Element p of column line g of a y pass (lines (z, kx), Nyquist lines z) or a
-// z pass (lines (ky, kx), Nyquist lines ky).
+// Column line g of a y pass (lines (z, kx), Nyquist lines z) or a z pass
+// (lines (ky, kx), Nyquist lines ky): element p is base + p*step.  Position p
+// of a y line is row w_row(z, p), linear in p; a z pass on this kernel has an
+// untiled workspace (z tile 1), so its rows w_row(p, ky) are linear in p too.
+template <typename T>
+struct ColLineG {
+    cx<T> *base;
+    size_t step;
+    __device__ __forceinline__ cx<T> &operator[](int p) const { return base[static_cast<size_t>(p) * step]; }
+};
 template <typename T, int MODE>
-__device__ __forceinline__ cx<T> *col_elem(const DevPlan &pl, cx<T> *W, cx<T> *Wn, bool nyq, long g, int p) {
+__device__ __forceinline__ ColLineG<T> col_line_g(const DevPlan &pl, cx<T> *W, cx<T> *Wn, bool nyq, long g) {
     const int nx = pl.nx, ny = pl.ny;
     if constexpr (MODE == Z_CONV) {
-        if (nyq) return Wn + static_cast<size_t>(p) * 2 * ny + g;
+        if (nyq) return ColLineG<T>{Wn + g, static_cast<size_t>(2) * ny};
         const int ky = static_cast<int>(g / nx), kx = static_cast<int>(g - static_cast<long>(ky) * nx);
-        return W + w_row(p, ky, ny, nx, pl.zb) + kx;
+        return ColLineG<T>{W + w_row(0, ky, ny, nx, 1) + kx, static_cast<size_t>(2) * ny * nx};
     } else {
-        if (nyq) return Wn + static_cast<size_t>(g) * 2 * ny + p;
+        if (nyq) return ColLineG<T>{Wn + static_cast<size_t>(g) * 2 * ny, 1};
         const int z = static_cast<int>(g / nx), kx = static_cast<int>(g - static_cast<long>(z) * nx);
-        return W + w_row(z, p, ny, nx, pl.zb) + kx;
+        return ColLineG<T>{W + w_row(z, 0, ny, nx, pl.zb) + kx, static_cast<size_t>(pl.zb) * nx};
     }
 }
 
@@ -132,7 +140,15 @@ __global__ void __launch_bounds__(kGenBlock) generic_kernel(const LaunchArgs arg
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr bool ROW = (MODE == X_FWD || MODE == X_INV);
     constexpr int axis = ROW ? 0 : (MODE == Z_CONV ? 2 : 1);
-    const int bid = static_cast<int>(blockIdx.x);
+    // XCD-aware order: workgroup b runs on XCD b mod 8; with the grid a whole
+    // number of rounds of 64, tiles are dealt to the XCDs in chunks of 8
+    // neighbours (chunk k to XCD k mod 8), so tiles that share 128-byte row
+    // segments meet in one L2
+    int bid = static_cast<int>(blockIdx.x);
+    if ((gridDim.x & 63) == 0) {
+        const int i = bid >> 3;
+        bid = (((i >> 3) << 3) + (bid & 7)) * 8 + (i & 7);
+    }
     if (bid >= args.nwg) return;
     int sgi = 0;
     while (sgi + 1 < args.nseg && bid >= args.seg[sgi + 1].wg_begin) ++sgi;
@@ -238,9 +254,10 @@ __global__ void __launch_bounds__(kGenBlock) generic_kernel(const LaunchArgs arg
             nout = MODE == Y_FWD ? L : ny;
         }
         const bool active = g < nlines;
+        const ColLineG<T> line = col_line_g<T, MODE>(pl, W, Wn, nyq, active ? g : 0);
         for (int p = m.j0; p < L; p += m.tpl) {
             cx<T> v = zero;
-            if (active && p < nin) v = *col_elem<T, MODE>(pl, W, Wn, nyq, g, p);
+            if (active && p < nin) v = line[p];
             A[gidx<false>(m.c, p, tile, L)] = v;
         }
         cx<T> *res;
@@ -266,7 +283,7 @@ __global__ void __launch_bounds__(kGenBlock) generic_kernel(const LaunchArgs arg
             res = gen_transform<T, MODE == Y_FWD ? -1 : +1, false>(A, B, m, tile, ax, tw);
         }
         if (active) {
-            for (int p = m.j0; p < nout; p += m.tpl) *col_elem<T, MODE>(pl, W, Wn, nyq, g, p) = res[gidx<false>(m.c, p, tile, L)];
+            for (int p = m.j0; p < nout; p += m.tpl) line[p] = res[gidx<false>(m.c, p, tile, L)];
         }
     }
 }

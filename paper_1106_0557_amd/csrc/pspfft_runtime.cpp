@@ -504,7 +504,10 @@ pspfft_status launch_generic_lines(int mode, const std::vector<int> &all, const 
             const size_t lds = bufs + (args.gtw ? ntw * csz : 0);
             PSPFFT_LOG(3, "pass %d prec %d generic: %d problems in %d segments, %ld workgroups of 256 threads, "
                           "%d lines each, %zu B LDS", mode, prec, args.count, args.nseg, wg, args.gtile, lds);
-            if (pspfft::launch_generic(mode, prec, args, static_cast<int>(wg), lds, stream) != hipSuccess)
+            // a whole number of rounds of 64 workgroups: the kernel deals its tiles to the XCDs in chunks
+            const long grid = (wg + 63) / 64 * 64;
+            if (grid > 0x7fffffffL) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+            if (pspfft::launch_generic(mode, prec, args, static_cast<int>(grid), lds, stream) != hipSuccess)
                 return PSPFFT_ERR_DEVICE;
         }
     }
