@@ -432,12 +432,17 @@ void pass_lines(int mode, const int n[3], long &main, long &nyq) {
 
 // Lines per workgroup of the generic kernel for lines of up to L points: the
 // largest power of two up to 64 whose two LDS buffers fit 160 KB, with at most
-// max(L, 4096) points per workgroup (about 16 per thread).  Its stage twiddles
-// go into LDS too where they fit beside the buffers.
+// max(2L, 2048) points per workgroup (about 8 per thread, two lines at least).
+// Its stage twiddles go into LDS too where they fit beside the buffers.
+// Measured (one solve, FP32): at most 2048 points instead of 4096 (more
+// workgroups per CU; with the chunked XCD order the narrower column tiles
+// still meet in L2) takes 480^3 from 13.5 to 12.4 ms and FP64 480^3 from 26.8
+// to 22.4 ms, but single-line tiles lose (960^3 y and z passes 17.0 / 66.4 ->
+// 21.0 / 80.4 ms), hence two lines at least.
 int generic_tile(int L, size_t csz) {
     int t = 64;
     while (t > 1 && (static_cast<size_t>(2) * t * (L + 1) * csz > 160 * 1024 ||
-                     static_cast<long>(t) * L > std::max(L, 4096)))
+                     static_cast<long>(t) * L > std::max(2L * L, 2048L)))
         t /= 2;
     return t;
 }
