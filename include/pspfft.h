@@ -165,11 +165,14 @@ int pspfft_plan_fused(pspfft_plan_t plan);
 
 /*
  * 1 if the plan keeps its spectrum kz-fastest, 0 otherwise (and for NULL).
- * That is the case where the z lines have three stages E, M, K with 16, 32 or
- * 64 threads per line (2 nz = 16*16*2, 36*4*4, 24*8*4 or 16*16*4, that is
- * nz = 256, 288, 384 or 512) and every array of a solve is below 4 GB: the z
- * pass then keeps each line within one wavefront, which reads its spectrum
- * values in contiguous runs.
+ * That is the case where the z pass keeps each line within one wavefront,
+ * which reads its spectrum values in contiguous runs: z lines of three stages
+ * E, M, K with 16, 32 or 64 threads per line (2 nz = 16*16*2, 36*4*4, 24*8*4,
+ * 16*16*4 or 24*8*8, that is nz = 256, 288, 384, 512 or 768), four-stage FP32
+ * lines of 32 or 64 threads (nz = 576, 1152, 320, 640), the FP32 32-family's
+ * 2048-point lines (nz = 1024), each where a z line's block of NB*2ny*nx
+ * positions stays below 4 GB; and z lines on the generic kernel (nz outside
+ * the radix families), whose lanes of a line walk consecutive kz.
  * pspfft_plan_green exports the same octant either way.
  */
 int pspfft_plan_spectrum_kz_fastest(pspfft_plan_t plan);

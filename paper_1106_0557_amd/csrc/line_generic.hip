@@ -270,10 +270,14 @@ __global__ void __launch_bounds__(kGenBlock) generic_kernel(const LaunchArgs arg
                 const int ky = nyq ? static_cast<int>(g) : static_cast<int>(g / nx);
                 const int kx = nyq ? nx : static_cast<int>(g - static_cast<long>(ky) * nx);
                 const int kyo = ky <= ny ? ky : 2 * ny - ky;
+                // plans with generic z lines keep the spectrum kz-fastest: octant value
+                // (kyo, kx, kzo) at (kyo*nx + kx)*(nz + 1) + kzo, Nyquist column kyo*(nz + 1) + kzo,
+                // so the lanes of a line read consecutive values
+                const T *gl = nyq ? Gn + static_cast<size_t>(kyo) * (nz + 1)
+                                  : G + (static_cast<size_t>(kyo) * nx + kx) * (nz + 1);
                 for (int kz = m.j0; kz < L; kz += m.tpl) {
                     const int kzo = kz <= nz ? kz : L - kz;
-                    const T gv = nyq ? Gn[static_cast<size_t>(kzo) * (ny + 1) + kyo]
-                                     : G[(static_cast<size_t>(kzo) * (ny + 1) + kyo) * nx + kx];
+                    const T gv = gl[kzo];
                     cx<T> &e = res[gidx<false>(m.c, kz, tile, L)];
                     e = cx<T>{e.x * gv, e.y * gv};
                 }

@@ -891,7 +891,9 @@ pspfft_status pspfft_plan_create_ex(int nx, int ny, int nz, const double h[3], p
         while (nbz > 0 && zb < cap && nbz % (2 * zb) == 0) zb *= 2;
         p->host.zb = zb;
     }
-    p->host.gz = z_wave_lines(p) ? 1 : 0;
+    // kz-fastest spectrum for wavefront-owned z lines and for z lines on the
+    // generic kernel (whose lanes of a line walk consecutive kz)
+    p->host.gz = z_wave_lines(p) || p->host.ax[2].E == 0 ? 1 : 0;
     // fused x-y plane kernels: nx == ny = E*K (at most two stages) and the plane fits in LDS
     {
         const AxisPlan &ax = p->host.ax[0];

@@ -158,3 +158,23 @@ def test_generic_and_family_problems_batched_equal_alone():
         w.close()
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("n,h", [((16, 8, 15), (0.02, 0.03, 0.025)), ((20, 12, 60), (0.05, 0.04, 0.03))])
+def test_generic_z_plans_keep_the_spectrum_kz_fastest(n, h):
+    """Plans whose z lines run on the generic kernel store the spectrum kz-fastest (the
+    lanes of a line read consecutive values) and still export the canonical octant
+    (Eq. greens_function transformed, checked against the oracle's)."""
+    from paper_1106_0557_amd import Plan
+
+    say(f"[generic z spectrum] n={n}")
+    want, _, abs_max = oracle.green_hat_octant(n, h)
+    for dtype, tol in ((torch.float64, FP64_TOL), (torch.float32, 1e-7)):
+        plan = Plan(*n, h=h, dtype=dtype)
+        assert plan.spectrum_kz_fastest
+        got = plan.green().double().cpu().numpy()
+        plan.close()
+        err = np.abs(got - want).max() / abs_max
+        say(f"  {dtype}: max err / max|G~| = {err:.3e}")
+        assert err <= tol
+    check(n, h)
