@@ -462,9 +462,10 @@ def test_config5_fp64_and_fp32_agree_on_every_cell():
 
 # FP32 meshes whose workspace passes 4 GB (64-bit addressing): x rows of 768 = 24*8*4,
 # y lines of 1536 = 24*8*8 and z lines of 1024 = 16*16*4; then y lines of 1152 =
-# 36*4*4*2 and z lines of 1280 = 20*4*4*4, the z lines kept within one wavefront
-# (64-bit bases per block of positions).
-@pytest.mark.parametrize("n", [(768, 768, 512), (768, 576, 640)])
+# 36*4*4*2 and z lines of 1280 = 20*4*4*4; z lines of 2048 (the 32-family, 32*32*2)
+# and of 1536 (24*8*8, a halved tile), the z lines always kept within one
+# wavefront (64-bit bases per block of positions).
+@pytest.mark.parametrize("n", [(768, 768, 512), (768, 576, 640), (512, 512, 1024), (640, 576, 768)])
 def test_fp32_arrays_above_4gb_sampled_direct_sum(n):
     """An FP32 mesh whose workspace passes 4 GB, checked at sampled targets by the direct sum."""
     from paper_1106_0557_amd import Plan, workspace_bytes
