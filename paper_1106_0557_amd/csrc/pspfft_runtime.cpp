@@ -612,7 +612,8 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
                 sg.wg_main = static_cast<int>(wm);
                 wg += (wm + wn) * sg.group;
             }
-            if (wg + 8 > 0x7fffffffL) return PSPFFT_ERR_UNSUPPORTED_SIZE;
+            // grids are padded to a multiple of 8 (XCD renumbering) or 64 (chunked tile order)
+            if (wg + 64 > 0x7fffffffL) return PSPFFT_ERR_UNSUPPORTED_SIZE;
             args.nwg = static_cast<int>(wg);
             args.xcd_remap = xcd_remap_mode(mode);
             args.wave_z = gz ? 1 : 0;
