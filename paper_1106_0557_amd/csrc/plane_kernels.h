@@ -276,7 +276,12 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
         load_even(pl);
         stage_nyquist();
         __syncthreads();  // twiddles and the first Nyquist column visible
-        for (;;) {
+        // One plane; false after the workgroup's last.  The first plane is a copy
+        // of its own, so that every entry to the loop follows a plane's stores:
+        // the compiler then counts those stores in its wait for the prefetched
+        // even rows, instead of draining them there (entered from the prologue,
+        // which stores nothing, the loop's waits assumed no stores in flight).
+        auto one_plane = [&]() __attribute__((always_inline)) -> bool {
             lanes();
             const PlaneRef r = plane_ref(args, pl);
             const uint32_t rs = rs_of(r);
@@ -343,10 +348,14 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
                 for (int m = 0; m < H; ++m) at<T>(plane, off + m * NB * CSZ) = v[m];
             }
             if (nxt < args.nwg) stage_nyquist();  // `sep` is free until the next y step
-            if (nxt >= args.nwg) break;
+            if (nxt >= args.nwg) return false;
             pl = nxt;
             __syncthreads();  // LDS readers of this plane are done
-        }
+            return true;
+        };
+        if (one_plane())
+            while (one_plane()) {
+            }
     }
 }
 
