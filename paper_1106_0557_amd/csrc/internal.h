@@ -84,6 +84,11 @@ struct Segment {
     int wg_main;      // tiles of main lines per problem; the rest are Nyquist lines
 };
 
+// Workspace bytes of a launch above which its line data is streamed with
+// nontemporal accesses: about the device's Infinity Cache (256 MB), which a
+// smaller launch's workspaces can stay in between passes.
+constexpr size_t kStreamBytes = size_t(256) << 20;
+
 struct LaunchArgs {
     int count;        // problems in this launch
     int nseg;         // segments
@@ -93,6 +98,8 @@ struct LaunchArgs {
     int gtile;        // generic line kernel: lines per workgroup (a power of two)
     int glmax;        // generic line kernel: longest line of the launch
     int gtw;          // generic line kernel: stage twiddles copied into LDS after the two buffers
+    int nt;           // streaming launch (workspaces beyond kStreamBytes): its line data takes
+                      // nontemporal loads and stores where the kernel says so
     Segment seg[kMaxProblems];
     ProbArg p[kMaxProblems];
 };

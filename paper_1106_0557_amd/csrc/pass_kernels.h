@@ -36,6 +36,18 @@ template <typename U>
 __device__ __forceinline__ const gbl<U> *as_global(const U *p) {
     return (const gbl<U> *)p;
 }
+// Nontemporal accesses of one complex value in global memory (streamed data
+// that should not displace what later accesses of the launch reuse).
+template <typename T>
+__device__ __forceinline__ void st_nt(cx<T> *p, cx<T> v) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(__builtin_bit_cast(v2, v), (__attribute__((address_space(1))) v2 *)(p));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> ld_nt(const cx<T> *p) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(cx<T>, __builtin_nontemporal_load((const __attribute__((address_space(1))) v2 *)(p)));
+}
 
 // Stage twiddle w of a table in LDS (a generic pointer) or in global memory.
 template <typename T>
@@ -310,7 +322,10 @@ struct LinePtrW {
 // lines, so the geometry is compile-time.  fix_off32(FIX): every array is below
 // 4 GB, so addresses use 32-bit lane offsets; otherwise (FIX & kFixWide) 64-bit
 // addresses.  FIX = 0: geometry from the plan at run time, 64-bit addresses.
-template <typename T, int E, int K, int MODE, int FIX>
+// NT (z lines of a streaming launch): the line is loaded and stored with
+// nontemporal accesses, so that it does not displace the spectrum, which the
+// launch's problems share.
+template <typename T, int E, int K, int MODE, int FIX, bool NT = false>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pass_kernel(const LaunchArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem);
@@ -565,7 +580,10 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         // read the whole line.
         constexpr int nload = (MODE == Y_INV) ? E : H;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = m < nload ? lane[m] : cx<T>{T(0), T(0)};
+        for (int m = 0; m < E; ++m) {
+            if constexpr (NT) v[m] = m < nload ? ld_nt(&lane[m]) : cx<T>{T(0), T(0)};
+            else v[m] = m < nload ? lane[m] : cx<T>{T(0), T(0)};
+        }
         if constexpr (MODE == Y_FWD) {
             FFT_F::template run<K>(v, ax, lds, ldsw, twl, c, t);
         } else if constexpr (MODE == Y_INV) {
@@ -606,7 +624,10 @@ __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E))) pa
         constexpr int nstore = (MODE == Y_FWD) ? E : H;
         if (active) {
 #pragma unroll
-            for (int m = 0; m < nstore; ++m) lane[m] = v[m];
+            for (int m = 0; m < nstore; ++m) {
+                if constexpr (NT) st_nt(&lane[m], v[m]);
+                else lane[m] = v[m];
+            }
         }
     }
 }
@@ -1147,12 +1168,14 @@ hipError_t launch_col(const LaunchArgs &args, int grid, int block, size_t lds, h
     static size_t seen_lds[kMaxDevices] = {0};
     auto fo = pass_kernel<T, E, K, MODE, FIX>;
     auto fp = col_persist_kernel<T, E, K, MODE, FIX>;
+    // z lines of a streaming launch: nontemporal line loads and stores
+    auto fs = pass_kernel<T, E, K, MODE, FIX, MODE == Z_CONV>;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     if (per_cu[dev] == 0 || seen_lds[dev] != lds) {
-        for (auto f : {fo, fp}) {
+        for (auto f : {fo, fp, fs}) {
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     160 * 1024);
             if (e != hipSuccess) return e;
@@ -1180,7 +1203,7 @@ hipError_t launch_col(const LaunchArgs &args, int grid, int block, size_t lds, h
         if (g > args.nwg) g = args.nwg;
         hipLaunchKernelGGL(fp, dim3(g), dim3(block), lds, stream, args);
     } else {
-        hipLaunchKernelGGL(fo, dim3(grid), dim3(block), lds, stream, args);
+        hipLaunchKernelGGL(args.nt ? fs : fo, dim3(grid), dim3(block), lds, stream, args);
     }
     return hipGetLastError();
 }

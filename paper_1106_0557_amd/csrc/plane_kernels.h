@@ -70,7 +70,9 @@ __device__ __forceinline__ PlaneRef plane_ref(const LaunchArgs &args, int pl) {
 // still covers most of the stores issued after them).  The inverse kernel loads the odd W rows of a plane while it transforms the even
 // ones, and the next plane's even rows (and Nyquist column) during the x step;
 // a whole plane of input would not fit in registers beside the one in use.
-template <typename T, int E, int K, bool FWD>
+// NT (inverse planes of a streaming launch): the W rows are loaded with
+// nontemporal accesses; they are read once.
+template <typename T, int E, int K, bool FWD, bool NT = false>
 __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args) {
     constexpr int n = E * K;
     constexpr int NB = K;
@@ -261,10 +263,14 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
 #pragma unroll
             for (int q = 0; q < NWV; ++q) {  // clamped, so every thread loads (no divergent definition)
                 const int i = tid + q * BLK;
-                nw[q] = Wnz[i < 2 * n ? i : 2 * n - 1];
+                if constexpr (NT) nw[q] = ld_nt(&Wnz[i < 2 * n ? i : 2 * n - 1]);
+                else nw[q] = Wnz[i < 2 * n ? i : 2 * n - 1];
             }
 #pragma unroll
-            for (int m = 0; m < E; ++m) e[m] = at<T>(Wz, even_off + m * 2 * NB * rs);
+            for (int m = 0; m < E; ++m) {
+                if constexpr (NT) e[m] = ld_nt(&at<T>(Wz, even_off + m * 2 * NB * rs));
+                else e[m] = at<T>(Wz, even_off + m * 2 * NB * rs);
+            }
         };
         auto stage_nyquist = [&]() {
 #pragma unroll
@@ -289,7 +295,10 @@ __global__ void __launch_bounds__(E * K * K) plane_kernel(const LaunchArgs args)
             const cx<T> *Wz = W_of(r);
             cx<T> o[E];  // odd rows, in flight while the even ones are transformed
 #pragma unroll
-            for (int m = 0; m < E; ++m) o[m] = at<T>(Wz, even_off + (m * 2 * NB + 1) * rs);
+            for (int m = 0; m < E; ++m) {
+                if constexpr (NT) o[m] = ld_nt(&at<T>(Wz, even_off + (m * 2 * NB + 1) * rs));
+                else o[m] = at<T>(Wz, even_off + (m * 2 * NB + 1) * rs);
+            }
             // the barrier before the loop or at the end of the previous plane
             // published the Nyquist column and retired the readers of the plane
             {  // y step: column kx = 0 also carries kx = n (as Y0 + i Yn)
@@ -379,14 +388,18 @@ hipError_t launch_plane_kernel(const LaunchArgs &args, size_t lds, hipStream_t s
     constexpr int kMaxDevices = 64;
     static int resident[kMaxDevices] = {0};
     auto fn = plane_kernel<T, E, K, FWD>;
+    // inverse planes of a streaming launch: nontemporal row loads
+    auto fs = plane_kernel<T, E, K, FWD, !FWD>;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     if (resident[dev] == 0) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                160 * 1024);
-        if (e != hipSuccess) return e;
+        for (auto f : {fn, fs}) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    160 * 1024);
+            if (e != hipSuccess) return e;
+        }
         int per_cu = 0, cus = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, E * K * K, lds);
         if (e != hipSuccess) return e;
@@ -404,7 +417,7 @@ hipError_t launch_plane_kernel(const LaunchArgs &args, size_t lds, hipStream_t s
                       (static_cast<long>(resident[dev]) * per);
     int grid = static_cast<int>(gens * resident[dev]);
     if (grid > args.nwg) grid = args.nwg;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(E * K * K), lds, stream, args);
+    hipLaunchKernelGGL(args.nt ? fs : fn, dim3(grid), dim3(E * K * K), lds, stream, args);
     return hipGetLastError();
 }
 

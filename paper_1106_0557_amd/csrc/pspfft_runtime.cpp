@@ -385,6 +385,14 @@ void destroy_plan(pspfft_plan_t p) {
 
 // Every device array of a solve (source, potential, workspace, spectrum) is
 // addressable with unsigned 32-bit byte offsets.
+// Launches whose workspaces together exceed the Infinity Cache stream their
+// line data (LaunchArgs::nt).
+bool streaming_launch(const pspfft_plan_t *plans, const std::vector<int> &idx, size_t c0, size_t c1) {
+    size_t b = 0;
+    for (size_t j = c0; j < c1; ++j) b += ws_bytes(plans[idx[j]]->n, plans[idx[j]]->prec);
+    return b > pspfft::kStreamBytes;
+}
+
 bool arrays_below_4gb(pspfft_plan_t p) {
     const size_t lim = size_t(1) << 32;
     const size_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
@@ -582,6 +590,7 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
             LaunchArgs args;
             std::memset(&args, 0, sizeof(args));
             args.count = static_cast<int>(c1 - c0);
+            args.nt = streaming_launch(plans, idx, c0, c1) ? 1 : 0;
             long wg = 0;
             for (size_t j = c0; j < c1; ++j) {
                 const int i = idx[j];
@@ -656,7 +665,8 @@ pspfft_status launch_lines(int mode, const std::vector<int> &all_in, const pspff
                 lds = static_cast<size_t>(a0.L) * (block / a0.NB) * csz;
             }
             PSPFFT_LOG(3, "pass %d prec %d E %d K %d fix %d: %d problems in %d segments, %ld workgroups of %d "
-                          "threads, %zu B LDS", mode, prec, E, K, fix, args.count, args.nseg, wg, block, lds);
+                          "threads, %zu B LDS, streaming %d", mode, prec, E, K, fix, args.count, args.nseg, wg, block,
+                       lds, args.nt);
             if (pspfft::launch_pass(mode, prec, E, K, fix, args, grid, block, lds, stream) != hipSuccess)
                 return PSPFFT_ERR_DEVICE;
         }
@@ -682,6 +692,7 @@ pspfft_status launch_planes(bool fwd, const std::vector<int> &all, const pspfft_
             LaunchArgs args;
             std::memset(&args, 0, sizeof(args));
             args.count = static_cast<int>(c1 - c0);
+            args.nt = streaming_launch(plans, idx, c0, c1) ? 1 : 0;
             for (size_t j = c0; j < c1; ++j) {
                 const int i = idx[j];
                 ProbArg &a = args.p[j - c0];
@@ -707,8 +718,8 @@ pspfft_status launch_planes(bool fwd, const std::vector<int> &all, const pspfft_
                 wg += nz * sg.group;
             }
             args.nwg = static_cast<int>(wg);
-            PSPFFT_LOG(3, "plane %s prec %d E %d K %d: %d problems, %ld workgroups of %d threads, %zu B LDS",
-                       fwd ? "fwd" : "inv", prec, E, K, args.count, wg, E * K * K, lds);
+            PSPFFT_LOG(3, "plane %s prec %d E %d K %d: %d problems, %ld workgroups of %d threads, %zu B LDS, "
+                          "streaming %d", fwd ? "fwd" : "inv", prec, E, K, args.count, wg, E * K * K, lds, args.nt);
             if (pspfft::launch_plane(fwd, prec, E, K, args, static_cast<int>(wg), lds, stream) != hipSuccess)
                 return PSPFFT_ERR_DEVICE;
         }

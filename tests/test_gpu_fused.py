@@ -8,7 +8,10 @@
   packed kx = 0 column), the y passes leave it untouched, and the fused inverse
   gives the oracle's potential;
 * fused and five-pass problems share grouped launches with results bit-identical
-  to solving alone, in place (S == Phi) included.
+  to solving alone, in place (S == Phi) included;
+* a batch whose workspaces pass the streaming threshold (nontemporal line
+  accesses in the z pass and the inverse plane pass) gives the bits of the
+  same problems solved alone, which stream nothing.
 """
 import sys
 
@@ -176,3 +179,31 @@ def test_fused_and_five_pass_problems_in_one_batch():
         w.close()
     for p in plans.values():
         p.close()
+
+
+@pytest.mark.parametrize("five", [False, True])
+def test_streaming_batch_equals_alone(five):
+    """Eight 128^3 FP32 problems (about 270 MB of workspaces, past the 256 MB
+    streaming threshold) in one batched call, against each solved alone."""
+    import paper_1106_0557_amd as ps
+
+    say(f"[streaming batch] 8 x 128^3 FP32, five_pass={five}")
+    mesh, h = (128, 128, 128), (1.0 / 128,) * 3
+    plan = ps.Plan(*mesh, h=h, dtype=torch.float32, five_pass=five)
+    assert 8 * plan.workspace_bytes() > 256 * 2**20
+    ws = [plan.workspace() for _ in range(8)]
+    S = [sources.random_field(mesh, seed=300 + k).to("cuda", torch.float32) for k in range(8)]
+    P = [torch.empty_like(s) for s in S]
+    ps.solve_batched(ws, S, P)
+    torch.cuda.synchronize()
+    for k in range(8):
+        alone = plan.solve(S[k])
+        torch.cuda.synchronize()
+        assert torch.equal(alone, P[k]), f"problem {k} differs between the streaming batch and alone"
+    want = oracle.solve_fft(S[0].double().cpu().numpy(), h)
+    err = norms.rel_l2(P[0].double().cpu().numpy(), want)
+    say(f"  rel l2 vs oracle {err:.3e}")
+    assert err <= FP32_TOL
+    for w in ws:
+        w.close()
+    plan.close()
