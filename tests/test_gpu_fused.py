@@ -190,7 +190,7 @@ def test_streaming_batch_equals_alone(five):
     say(f"[streaming batch] 8 x 128^3 FP32, five_pass={five}")
     mesh, h = (128, 128, 128), (1.0 / 128,) * 3
     plan = ps.Plan(*mesh, h=h, dtype=torch.float32, five_pass=five)
-    assert 8 * plan.workspace_bytes() > 256 * 2**20
+    assert 8 * plan.workspace_bytes > 256 * 2**20
     ws = [plan.workspace() for _ in range(8)]
     S = [sources.random_field(mesh, seed=300 + k).to("cuda", torch.float32) for k in range(8)]
     P = [torch.empty_like(s) for s in S]
