@@ -181,29 +181,31 @@ def test_fused_and_five_pass_problems_in_one_batch():
         p.close()
 
 
-@pytest.mark.parametrize("five", [False, True])
-def test_streaming_batch_equals_alone(five):
-    """Eight 128^3 FP32 problems (about 270 MB of workspaces, past the 256 MB
-    streaming threshold) in one batched call, against each solved alone."""
+@pytest.mark.parametrize("dtype,five,count", [(torch.float32, False, 8), (torch.float32, True, 8),
+                                               (torch.float64, False, 4)])
+def test_streaming_batch_equals_alone(dtype, five, count):
+    """128^3 problems whose workspaces together pass the 256 MB streaming
+    threshold (eight FP32 or four FP64) in one batched call, against each
+    solved alone (below the threshold)."""
     import paper_1106_0557_amd as ps
 
-    say(f"[streaming batch] 8 x 128^3 FP32, five_pass={five}")
+    say(f"[streaming batch] {count} x 128^3 {dtype}, five_pass={five}")
     mesh, h = (128, 128, 128), (1.0 / 128,) * 3
-    plan = ps.Plan(*mesh, h=h, dtype=torch.float32, five_pass=five)
-    assert 8 * plan.workspace_bytes > 256 * 2**20
-    ws = [plan.workspace() for _ in range(8)]
-    S = [sources.random_field(mesh, seed=300 + k).to("cuda", torch.float32) for k in range(8)]
+    plan = ps.Plan(*mesh, h=h, dtype=dtype, five_pass=five)
+    assert count * plan.workspace_bytes > 256 * 2**20 >= plan.workspace_bytes
+    ws = [plan.workspace() for _ in range(count)]
+    S = [sources.random_field(mesh, seed=300 + k).to("cuda", dtype) for k in range(count)]
     P = [torch.empty_like(s) for s in S]
     ps.solve_batched(ws, S, P)
     torch.cuda.synchronize()
-    for k in range(8):
+    for k in range(count):
         alone = plan.solve(S[k])
         torch.cuda.synchronize()
         assert torch.equal(alone, P[k]), f"problem {k} differs between the streaming batch and alone"
     want = oracle.solve_fft(S[0].double().cpu().numpy(), h)
     err = norms.rel_l2(P[0].double().cpu().numpy(), want)
     say(f"  rel l2 vs oracle {err:.3e}")
-    assert err <= FP32_TOL
+    assert err <= (FP32_TOL if dtype == torch.float32 else FP64_TOL)
     for w in ws:
         w.close()
     plan.close()
