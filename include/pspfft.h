@@ -257,7 +257,11 @@ pspfft_status pspfft_solve_ws(pspfft_plan_t plan, pspfft_workspace_t ws, const v
  * joined back into `stream` by events: the batch is ordered after the work
  * queued on `stream` before the call and before the work queued after it, as
  * if it ran on `stream`.  Results do not depend on what else is in the batch:
- * every problem is cut into the same tiles whatever its neighbours.
+ * every problem is cut into the same tiles whatever its neighbours.  A launch
+ * whose problems' workspaces together exceed 256 MB (about the device's
+ * Infinity Cache) streams its line data through nontemporal loads and stores
+ * in the z pass and the inverse plane pass; the arithmetic and the results are
+ * the same.
  */
 pspfft_status pspfft_solve_batched(int count, const pspfft_plan_t *plans, const pspfft_workspace_t *ws,
                                    const void *const *S, void *const *Phi, hipStream_t stream);
