@@ -667,16 +667,17 @@ __device__ __forceinline__ TileWalk tile_walk() {
 // Store of one complex value through a raw buffer resource: a store at or past
 // `bytes` is dropped by the hardware's range check, so lanes without a line
 // store nothing without a branch around the store.
-template <typename T>
+// NT: a nontemporal store (cache-policy bit 1).
+template <typename T, bool NT = false>
 __device__ __forceinline__ void buffer_store(const cx<T> v, char *base, uint32_t bytes, uint32_t off) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, static_cast<short>(0),
                                                                         static_cast<int>(bytes), 0x00020000);
     if constexpr (sizeof(T) == 4) {
         typedef unsigned u2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, NT ? 2 : 0);
     } else {
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rs, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rs, off, 0, NT ? 2 : 0);
     }
 }
 
@@ -839,7 +840,7 @@ __device__ __forceinline__ ZLine<T> y_line(const LaunchArgs &args, int bid, int 
 // loop is entered with nothing outstanding, and plan fields are read through
 // the constant address space (scalar loads; a vector load there would wait for
 // the previous tile's stores).  Otherwise the workgroup takes one tile.
-template <typename T, int E, int K, int MODE, bool PERSIST, int ST = 3, bool WIDE = false>
+template <typename T, int E, int K, int MODE, bool PERSIST, int ST = 3, bool WIDE = false, bool NT = false>
 __global__ void __launch_bounds__((max_block_for(sizeof(T) == 4 ? 0 : 1, E)))
 __attribute__((amdgpu_waves_per_eu(wave_waves_per_simd(sizeof(T) == 4 ? 0 : 1, MODE, E,
                                                        wave_nb(E, K, ST), ST))))
@@ -906,7 +907,7 @@ wave_col_kernel(const LaunchArgs args) {
         // while the spectrum values are still in flight)
         cx<T> first[NLOAD];
 #pragma unroll
-        for (int m = 0; m < NLOAD; ++m) first[m] = cur.lane[m];
+        for (int m = 0; m < NLOAD; ++m) first[m] = NT ? ld_nt(&cur.lane[m]) : cur.lane[m];
         load_g(bid, gnx);
 #pragma unroll
         for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = first[m];
@@ -914,7 +915,7 @@ wave_col_kernel(const LaunchArgs args) {
         // FP64: sixteen-byte values held there do not stay in registers
         load_g(bid, gnx);
 #pragma unroll
-        for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = cur.lane[m];
+        for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = NT ? ld_nt(&cur.lane[m]) : cur.lane[m];
     }
     if constexpr (PERSIST) __builtin_amdgcn_s_waitcnt(0x0f70);  // nothing outstanding on entry (vmcnt 0)
     for (;;) {
@@ -941,7 +942,7 @@ wave_col_kernel(const LaunchArgs args) {
             fol = line(fbid);
             if constexpr (PF) {
 #pragma unroll
-                for (int m = 0; m < NLOAD; ++m) nxt[m] = fol.lane[m];
+                for (int m = 0; m < NLOAD; ++m) nxt[m] = NT ? ld_nt(&fol.lane[m]) : fol.lane[m];
             }
             load_g(fbid, gnx);
         }
@@ -954,12 +955,12 @@ wave_col_kernel(const LaunchArgs args) {
 #pragma unroll
         for (int m = 0; m < NSTORE; ++m) {
             if constexpr (WIDE) {
-                buffer_store<T>(rowc[m * RM], cur.lane.block(m), cur.bytes,
-                                cur.active ? static_cast<uint32_t>(cur.lane.lane) : 0xfffffff0u);
+                buffer_store<T, NT>(rowc[m * RM], cur.lane.block(m), cur.bytes,
+                                    cur.active ? static_cast<uint32_t>(cur.lane.lane) : 0xfffffff0u);
             } else {
                 const uint32_t off = static_cast<uint32_t>(cur.lane.lane) +
                                      static_cast<uint32_t>(m) * static_cast<uint32_t>(cur.lane.step);
-                buffer_store<T>(rowc[m * RM], cur.lane.base, cur.bytes, cur.active ? off : 0xfffffff0u);
+                buffer_store<T, NT>(rowc[m * RM], cur.lane.base, cur.bytes, cur.active ? off : 0xfffffff0u);
             }
         }
         if (!more) break;
@@ -969,7 +970,7 @@ wave_col_kernel(const LaunchArgs args) {
             for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = nxt[m];
         } else {
 #pragma unroll
-            for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = fol.lane[m];
+            for (int m = 0; m < NLOAD; ++m) rowc[m * RM] = NT ? ld_nt(&fol.lane[m]) : fol.lane[m];
         }
         cur = fol;
         bid = nbid;
@@ -1223,12 +1224,17 @@ hipError_t launch_wave_col(const LaunchArgs &args, hipStream_t stream) {
     static int per_cu[kMaxDevices] = {0}, cus[kMaxDevices] = {0};
     auto fp = wave_col_kernel<T, E, K, MODE, true, ST, WIDE>;
     auto fo = wave_col_kernel<T, E, K, MODE, false, ST, WIDE>;
+    // FP32 z lines below 4 GB of a streaming launch: nontemporal line loads and stores
+    constexpr bool NTZ = MODE == Z_CONV && sizeof(T) == 4 && !WIDE;
+    auto fpn = wave_col_kernel<T, E, K, MODE, true, ST, WIDE, NTZ>;
+    auto fon = wave_col_kernel<T, E, K, MODE, false, ST, WIDE, NTZ>;
+    const bool nt = NTZ && args.nt;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
     if (per_cu[dev] == 0) {
-        for (auto f : {fp, fo}) {
+        for (auto f : {fp, fo, fpn, fon}) {
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     160 * 1024);
             if (e != hipSuccess) return e;
@@ -1245,12 +1251,12 @@ hipError_t launch_wave_col(const LaunchArgs &args, hipStream_t stream) {
     if (mode == 1 || (mode < 0 && per_cu[dev] == 1)) {
         int grid = per_cu[dev] * cus[dev];
         if (grid > args.nwg) grid = args.nwg;
-        hipLaunchKernelGGL(fp, dim3(grid), dim3(block), lds, stream, args);
+        hipLaunchKernelGGL(nt ? fpn : fp, dim3(grid), dim3(block), lds, stream, args);
     } else {
         // chunked tile order (tile_walk): a grid of whole chunk rounds (8 XCDs x kTileChunk)
         constexpr int round = E != 16 ? 8 * kTileChunk : 1;
         const int grid = (args.nwg + round - 1) / round * round;
-        hipLaunchKernelGGL(fo, dim3(grid), dim3(block), lds, stream, args);
+        hipLaunchKernelGGL(nt ? fon : fo, dim3(grid), dim3(block), lds, stream, args);
     }
     return hipGetLastError();
 }
