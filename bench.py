@@ -86,6 +86,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--settle-s", type=float, default=0.25,
+                    help="untimed steps for this many seconds before the warmup steps, so that the GPU's clocks "
+                         "reach their steady state (measured: a few warm-up steps from idle leave the timed steps "
+                         "about 5 %% slow)")
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--batch", type=int, default=32, help="FP32 solves per served step")
     ap.add_argument("--fp64-solves", type=int, default=2500, help="sequential FP64 plain solves (paper: 2500)")
@@ -155,7 +159,15 @@ def main():
         if evs is not None:
             evs[len(active)].record(stream)
 
-    log(f"[bench] warmup {args.warmup} steps")
+    settle_steps = 0
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < args.settle_s:
+        for _ in range(8):
+            step()
+        settle_steps += 8
+        torch.cuda.synchronize()
+    settle_s = time.perf_counter() - t_settle
+    log(f"[bench] settled for {settle_s:.2f} s ({settle_steps} untimed steps); warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -421,6 +433,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle": {"seconds": round(settle_s, 3), "steps": settle_steps,
+                   "note": "untimed steps before the warmup steps, until the GPU's clocks are steady"},
         "ms_per_step": round(wall / args.steps * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",

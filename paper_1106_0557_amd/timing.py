@@ -4,7 +4,8 @@
 
 For each mesh n^3 (unit box, h = 1/n) the source is the 512^3 benchmark's kind:
 64 Gaussian blobs plus a sphere of radius 0.2 (sources.config5).  The plan and
-one workspace are built, two solves warm up, and each of `reps` solves runs
+one workspace are built, solves run untimed for at least a quarter of a second
+(at least two; from idle the GPU's clocks need about that long to settle), and each of `reps` solves runs
 pass by pass on one stream with HIP events between the passes.  One line per
 mesh: the mean milliseconds of every active pass and of the whole solve, and
 the solve's algorithmic bytes (the sum of its passes' bytes, Plan.solve_bytes)
@@ -13,6 +14,7 @@ over its time.  The kernels run through the C ABI like any solve.
 import argparse
 import json
 import sys
+import time
 
 
 def main(argv=None):
@@ -41,9 +43,11 @@ def main(argv=None):
         plan = ps.Plan(n, n, n, h=h, dtype=dt)
         w = plan.workspace()
         out = torch.empty_like(src)
-        for _ in range(2):
+        t_settle, k = time.perf_counter(), 0
+        while k < 2 or time.perf_counter() - t_settle < 0.25:
             ps.solve_batched([w], [src], [out])
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            k += 1
         active = plan.active_passes
         tot = {p: 0.0 for p in active}
         for _ in range(args.reps):

@@ -181,18 +181,23 @@ def test_fused_and_five_pass_problems_in_one_batch():
         p.close()
 
 
-@pytest.mark.parametrize("dtype,five,count", [(torch.float32, False, 8), (torch.float32, True, 8),
-                                               (torch.float64, False, 4)])
-def test_streaming_batch_equals_alone(dtype, five, count):
-    """128^3 problems whose workspaces together pass the 256 MB streaming
-    threshold (eight FP32 or four FP64) in one batched call, against each
-    solved alone (below the threshold)."""
+@pytest.mark.parametrize("mesh,dtype,five,count", [((128, 128, 128), torch.float32, False, 8),
+                                                    ((128, 128, 128), torch.float32, True, 8),
+                                                    ((128, 128, 128), torch.float64, False, 4),
+                                                    ((128, 128, 256), torch.float32, False, 4)])
+def test_streaming_batch_equals_alone(mesh, dtype, five, count):
+    """Problems whose workspaces together pass the 256 MB streaming threshold
+    (eight FP32 or four FP64 128^3 meshes; four 128x128x256 meshes, whose z
+    lines of 512 points lie within one wavefront) in one batched call, against
+    each solved alone (below the threshold)."""
     import paper_1106_0557_amd as ps
 
-    say(f"[streaming batch] {count} x 128^3 {dtype}, five_pass={five}")
-    mesh, h = (128, 128, 128), (1.0 / 128,) * 3
+    say(f"[streaming batch] {count} x {mesh} {dtype}, five_pass={five}")
+    h = tuple(1.0 / m for m in mesh)
     plan = ps.Plan(*mesh, h=h, dtype=dtype, five_pass=five)
     assert count * plan.workspace_bytes > 256 * 2**20 >= plan.workspace_bytes
+    if mesh[2] == 256:
+        assert plan.spectrum_kz_fastest  # wavefront-owned z lines
     ws = [plan.workspace() for _ in range(count)]
     S = [sources.random_field(mesh, seed=300 + k).to("cuda", dtype) for k in range(count)]
     P = [torch.empty_like(s) for s in S]
